@@ -1,0 +1,199 @@
+/*
+ * m4.h -- exact counts of the six connected induced 4-node motifs on an
+ * AMD MI355X (gfx950), C ABI.
+ *
+ * Problem (HARP-ME, Section II): G = (V, E) is a simple undirected graph.  An
+ * induced occurrence of a connected 4-node pattern p is a 4-vertex subset S
+ * whose induced subgraph G[S] is isomorphic to p; N_p is the number of such
+ * subsets.  The library returns N_p for the six connected 4-node patterns in
+ * this order (m4_motif):
+ *
+ *   [0] 3-star (claw)   [1] 4-path   [2] tailed triangle (paw)
+ *   [3] 4-cycle         [4] diamond  [5] 4-clique
+ *
+ * Method (Section III): only an anchor basis is enumerated -- per-edge
+ * triangle counts t_e, 4-cliques and non-induced 4-cycles, found by sorted
+ * neighbour-list intersections over a degree-oriented CSR (Section III-D) --
+ * and the remaining counts follow from exact closure relations over degrees,
+ * wedges and t_e (Section III-F).
+ *
+ * Conventions for every entry point:
+ *   - Return value is an m4_status; outputs are untouched on error.
+ *   - The caller owns every input and output buffer.  The library keeps no
+ *     caller pointer after a call returns.
+ *   - Device pointers refer to memory of the context's device.
+ *   - A context is not thread-safe: one host thread per context at a time.
+ *   - Nothing throws across this boundary.
+ */
+#ifndef M4_H
+#define M4_H
+#include <stddef.h>
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  M4_OK = 0,
+  M4_EINVAL = 1,    /* bad argument, or a CSR that is not simple/symmetric/
+                       sorted (detected only with M4_VALIDATE)               */
+  M4_ERANGE = 2,    /* n >= 2^31, nnz >= 2^31, or nnz != row_ptr[n]          */
+  M4_EOVERFLOW = 3, /* a count, or an intermediate sum, is >= 2^64          */
+  M4_ENOMEM = 4,    /* device or pinned host allocation failed, or the
+                       device budget cannot hold even one partition        */
+  M4_EDEVICE = 5,   /* a HIP call failed; m4_last_error() has the text      */
+  M4_EBUSY = 6,     /* server queue full                                    */
+  M4_EINTERNAL = 7  /* internal consistency check failed (a library bug)    */
+} m4_status;
+
+typedef enum {
+  M4_STAR = 0, M4_PATH = 1, M4_PAW = 2, M4_CYCLE = 3, M4_DIAMOND = 4, M4_CLIQUE = 5
+} m4_motif;
+
+/* Symmetric CSR of a simple undirected graph: row v lists N(v), strictly
+ * increasing, without v itself; every edge appears in both rows.  nnz = 2|E|.
+ * on_device = 1: row_ptr/col are device pointers, 0: host pointers. */
+typedef struct {
+  int64_t n;
+  int64_t nnz;
+  const int64_t* row_ptr; /* int64[n+1] */
+  const int32_t* col;     /* int32[nnz] */
+  int32_t on_device;
+} m4_csr;
+
+/* option flags */
+#define M4_VALIDATE 0x1u        /* check the CSR on the device first (O(m log d)) */
+#define M4_NO_CACHE 0x2u        /* disable induced-signature frontier reuse         */
+#define M4_FORCE_PARTITION 0x4u /* take the halo-partition path even if it fits      */
+#define M4_STATS 0x8u           /* fill the work counters of m4_stats               */
+#define M4_TIMING 0x10u         /* time every kernel launch with HIP events         */
+
+typedef struct {
+  uint64_t device_budget_bytes; /* 0 = no budget (whole device)                    */
+  uint32_t flags;               /* M4_* flags above                                */
+  uint32_t cache_rows;          /* signature-cache rows per owner (0 = unlimited)  */
+  void* hip_stream;             /* hipStream_t to run on (NULL = context stream)   */
+  /* tuning (0 = library default / autotuned value) */
+  int32_t tri_wave_max;   /* owners with out-degree <= this use one wavefront      */
+  int32_t c4_light_max;   /* owners with wedge bound <= this use the LDS hash      */
+  int32_t reserved[4];
+} m4_opts;
+
+/* Kernel slots of m4_stats.ms_kernel / k_* (one slot per kernel launch of
+ * the resident pipeline; M4_K_BUILD covers all CSR-builder kernels). */
+enum {
+  M4_K_BUILD = 0,     /* degrees, degree sort, relabel + row sort, offsets      */
+  M4_K_TRI_GLOBAL,    /* triangle/4-clique owners, out-degree > 1024           */
+  M4_K_TRI_1024,      /* ... out-degree in (512, 1024], bitmap rows in LDS      */
+  M4_K_TRI_512,       /* ... (256, 512]                                        */
+  M4_K_TRI_256,       /* ... (128, 256]                                        */
+  M4_K_TRI_128,       /* ... (wave max, 128]                                   */
+  M4_K_TRI_WAVE,      /* ... out-degree <= 64, one wavefront per owner         */
+  M4_K_C4_PLAN,       /* 4-cycle wedge bounds and owner buckets                 */
+  M4_K_C4_WIN16,      /* 4-cycle owners with windowed 16-bit LDS counters      */
+  M4_K_C4_WIN32,      /* ... windowed 32-bit LDS counters                      */
+  M4_K_C4_HASH,       /* ... LDS hash table                                    */
+  M4_K_CLOSURE,       /* closure sums and exact inverse                         */
+  M4_NK = 16
+};
+
+/* Work and timing counters of one call.  basis[] is filled for every call
+ * with a non-NULL m4_stats; the k_* counters need M4_STATS and ms_kernel[]
+ * needs M4_TIMING.  Per slot:
+ *   triangle slots: k_elems = list elements looked up, k_rows = owners,
+ *                   k_aux = out-list entries of the owners, k_aux2 = triangles
+ *   4-cycle slots:  k_elems = wedge endpoints counted, k_rows = owners,
+ *                   k_aux = lower neighbours (segments), k_aux2 = segment
+ *                   visits (window slots) or row entries read (hash slot)
+ *   closure:        k_elems = oriented edges, k_rows = vertices
+ *   build:          k_elems = CSR entries, k_rows = vertices */
+typedef struct {
+  /* non-induced basis: T, K4, C4_ni, S = sum C(d,3), P_ni, Paw_ni, D_ni,
+   * sum_e t_e (each < 2^64, else the call returns M4_EOVERFLOW) */
+  uint64_t basis[8];
+  uint64_t intersect_steps; /* sorted-list elements looked up (triangle anchors) */
+  uint64_t wedges;          /* 4-cycle wedge endpoints counted                   */
+  uint64_t cache_lookups;   /* frontier requests of the 4-clique stage           */
+  uint64_t cache_hits;      /* ... served from the signature cache               */
+  uint64_t partitions;      /* halo partitions processed (1 = resident)          */
+  uint64_t h2d_bytes;       /* host-to-device bytes moved by the call            */
+  uint64_t halo_rows;       /* rows copied as halo over all partitions           */
+  uint64_t k_elems[M4_NK], k_rows[M4_NK], k_aux[M4_NK], k_aux2[M4_NK];
+  double ms_kernel[M4_NK];  /* per-slot kernel time (M4_TIMING)                  */
+  double ms_total, ms_build, ms_tri, ms_c4, ms_closure, ms_h2d;
+} m4_stats;
+
+typedef struct m4_ctx m4_ctx;
+
+/* Context bound to one device.  It owns a stream, a growable device
+ * workspace and pinned staging buffers; reuse it across calls so that the
+ * steady state allocates nothing. */
+int m4_ctx_create(int device, m4_ctx** out);
+void m4_ctx_destroy(m4_ctx* ctx);
+/* Text of the last error raised in this context (never NULL). */
+const char* m4_last_error(const m4_ctx* ctx);
+const char* m4_strerror(int status);
+
+/* Blocking count on device 0 with a process-wide default context. */
+int m4_count_motifs4(const m4_csr* g, uint64_t out[6]);
+
+/* Full entry point: counts on ctx's device, blocking until out[] is written.
+ * opts and st may be NULL. */
+int m4_count_motifs4_ex(m4_ctx* ctx, const m4_csr* g, const m4_opts* opts,
+                        uint64_t out[6], m4_stats* st);
+
+/* Per-edge triangle counts t_e = |N(u) & N(v)| for every CSR entry of g, in
+ * g's own layout (t_out[p] for col[p]); t_out is a device pointer when
+ * g->on_device, else host.  Same anchor kernels as the count. */
+int m4_edge_triangles(m4_ctx* ctx, const m4_csr* g, const m4_opts* opts,
+                      uint32_t* t_out);
+
+/* ---------------------------------------------------------------- batch --
+ * Many independent graphs packed in one arena: graph i has vertices
+ * [voff[i], voff[i+1]) and CSR entries [eoff[i], eoff[i+1]) of row_ptr/col;
+ * row_ptr holds local offsets (row_ptr[voff[i]] == 0 for every graph ... see
+ * layout below) and col holds LOCAL vertex ids in [0, n_i).
+ *   row_ptr: int64[voff[G] + G]  -- graph i uses row_ptr[voff[i] + i ...
+ *            voff[i+1] + i], its own n_i + 1 offsets starting at 0
+ *   col    : int32[eoff[G]]      -- graph i uses col[eoff[i] ... eoff[i+1])
+ * All arrays live on the device when on_device, else on the host.  out is a
+ * host array of G * 6 counts.  One persistent launch counts every graph. */
+typedef struct {
+  int64_t num_graphs;
+  const int64_t* voff;    /* int64[G+1] */
+  const int64_t* eoff;    /* int64[G+1] */
+  const int64_t* row_ptr; /* int64[voff[G] + G] */
+  const int32_t* col;     /* int32[eoff[G]] */
+  int32_t on_device;
+} m4_batch;
+
+int m4_count_batch(m4_ctx* ctx, const m4_batch* b, const m4_opts* opts,
+                   uint64_t* out, m4_stats* st);
+
+/* -------------------------------------------------------------- serving --
+ * A request loop with continuous batching: submitted graphs are copied into
+ * pinned staging, admitted to the device while their CSR and work arrays fit
+ * the HBM budget, and counted together with whatever else is resident. */
+typedef struct m4_server m4_server;
+typedef struct {
+  uint64_t id;       /* value returned by m4_server_submit */
+  uint64_t tag;      /* caller tag                          */
+  int32_t status;    /* m4_status of this request           */
+  uint64_t counts[6];
+  double t_submit_ms, t_admit_ms, t_done_ms; /* server clock */
+} m4_result;
+
+int m4_server_create(m4_ctx* ctx, uint64_t hbm_budget_bytes, int max_queue,
+                     m4_server** out);
+int m4_server_submit(m4_server* s, const m4_csr* g, uint64_t tag, uint64_t* id);
+int m4_server_poll(m4_server* s, m4_result* res, int max_results, int* got);
+/* Blocks until every submitted request has a result ready for polling. */
+int m4_server_drain(m4_server* s);
+void m4_server_destroy(m4_server* s);
+/* Milliseconds on the server clock (the clock of m4_result times). */
+double m4_server_now_ms(const m4_server* s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,294 @@
+"""Python binding of libm4 -- exact connected induced 4-node motif counts on
+AMD MI355X (gfx950).
+
+Argument marshalling only: every step of the count runs in the HIP kernels
+of ``libm4.so`` (``csrc/``), reached through its C ABI (``include/m4.h``).
+There is no CPU fallback: if the library is missing or no GPU is present the
+calls raise.  torch is used for device memory and streams only.
+
+Counts are returned as Python ints in the order
+``(3-star, 4-path, tailed triangle, 4-cycle, diamond, 4-clique)``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libm4.so")
+
+M4_OK, M4_EINVAL, M4_ERANGE, M4_EOVERFLOW, M4_ENOMEM, M4_EDEVICE, M4_EBUSY, M4_EINTERNAL = range(8)
+M4_VALIDATE, M4_NO_CACHE, M4_FORCE_PARTITION, M4_STATS, M4_TIMING = 0x1, 0x2, 0x4, 0x8, 0x10
+M4_NK = 16
+KERNELS = ("build", "tri_global", "tri_1024", "tri_512", "tri_256", "tri_128", "tri_wave",
+           "c4_plan", "c4_win16", "c4_win32", "c4_hash", "closure")
+NAMES = ("star", "path", "paw", "cycle", "diamond", "clique")
+BASIS = ("T", "K4", "C4_ni", "S", "P_ni", "Paw_ni", "D_ni", "sum_t")
+
+
+class M4Error(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"m4 error {code}: {msg}")
+        self.code = code
+
+
+class Csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p),
+                ("on_device", ctypes.c_int32)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("device_budget_bytes", ctypes.c_uint64), ("flags", ctypes.c_uint32),
+                ("cache_rows", ctypes.c_uint32), ("hip_stream", ctypes.c_void_p),
+                ("tri_wave_max", ctypes.c_int32), ("c4_light_max", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("basis", ctypes.c_uint64 * 8), ("intersect_steps", ctypes.c_uint64),
+                ("wedges", ctypes.c_uint64), ("cache_lookups", ctypes.c_uint64),
+                ("cache_hits", ctypes.c_uint64), ("partitions", ctypes.c_uint64),
+                ("h2d_bytes", ctypes.c_uint64), ("halo_rows", ctypes.c_uint64),
+                ("k_elems", ctypes.c_uint64 * M4_NK), ("k_rows", ctypes.c_uint64 * M4_NK),
+                ("k_aux", ctypes.c_uint64 * M4_NK), ("k_aux2", ctypes.c_uint64 * M4_NK),
+                ("ms_kernel", ctypes.c_double * M4_NK),
+                ("ms_total", ctypes.c_double), ("ms_build", ctypes.c_double),
+                ("ms_tri", ctypes.c_double), ("ms_c4", ctypes.c_double),
+                ("ms_closure", ctypes.c_double), ("ms_h2d", ctypes.c_double)]
+
+    def to_dict(self):
+        d = {k: int(v) for k, v in zip(BASIS, self.basis)}
+        for f, _ in self._fields_[1:]:
+            v = getattr(self, f)
+            d[f] = list(v) if isinstance(v, ctypes.Array) else v
+        return d
+
+
+class Batch(ctypes.Structure):
+    _fields_ = [("num_graphs", ctypes.c_int64), ("voff", ctypes.c_void_p),
+                ("eoff", ctypes.c_void_p), ("row_ptr", ctypes.c_void_p),
+                ("col", ctypes.c_void_p), ("on_device", ctypes.c_int32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("tag", ctypes.c_uint64), ("status", ctypes.c_int32),
+                ("counts", ctypes.c_uint64 * 6), ("t_submit_ms", ctypes.c_double),
+                ("t_admit_ms", ctypes.c_double), ("t_done_ms", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libm4.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        # torch ships its own HIP runtime with the same soname; loading it
+        # first makes libm4 bind to that one runtime, so device pointers and
+        # streams from torch are valid in the library.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        if not os.path.exists(LIB_PATH):
+            raise M4Error(M4_EDEVICE, f"{LIB_PATH} is missing: run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        p, i, u64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64
+        L.m4_ctx_create.argtypes = [i, ctypes.POINTER(p)]
+        L.m4_ctx_destroy.argtypes = [p]
+        L.m4_ctx_destroy.restype = None
+        L.m4_last_error.argtypes = [p]
+        L.m4_last_error.restype = ctypes.c_char_p
+        L.m4_strerror.argtypes = [i]
+        L.m4_strerror.restype = ctypes.c_char_p
+        L.m4_count_motifs4.argtypes = [ctypes.POINTER(Csr), p]
+        L.m4_count_motifs4_ex.argtypes = [p, ctypes.POINTER(Csr), ctypes.POINTER(Opts), p,
+                                          ctypes.POINTER(Stats)]
+        L.m4_edge_triangles.argtypes = [p, ctypes.POINTER(Csr), ctypes.POINTER(Opts), p]
+        L.m4_count_batch.argtypes = [p, ctypes.POINTER(Batch), ctypes.POINTER(Opts), p,
+                                     ctypes.POINTER(Stats)]
+        L.m4_server_create.argtypes = [p, u64, i, ctypes.POINTER(p)]
+        L.m4_server_submit.argtypes = [p, ctypes.POINTER(Csr), u64, ctypes.POINTER(u64)]
+        L.m4_server_poll.argtypes = [p, ctypes.POINTER(Result), i, ctypes.POINTER(i)]
+        L.m4_server_drain.argtypes = [p]
+        L.m4_server_destroy.argtypes = [p]
+        L.m4_server_destroy.restype = None
+        L.m4_server_now_ms.argtypes = [p]
+        L.m4_server_now_ms.restype = ctypes.c_double
+        _lib = L
+    return _lib
+
+
+def _is_torch(x):
+    return type(x).__module__.startswith("torch")
+
+
+class _Keep:
+    """Holds converted arrays alive for the duration of a call."""
+
+    def __init__(self):
+        self.refs = []
+
+
+def make_csr(row_ptr, col, keep: _Keep) -> Csr:
+    """Csr view of (row_ptr int64[n+1], col int32[nnz]): numpy arrays (host)
+    or torch tensors (device when they live on a GPU)."""
+    if _is_torch(row_ptr):
+        import torch
+        rp = row_ptr.to(torch.int64).contiguous()
+        c = col.to(torch.int32).contiguous()
+        keep.refs += [rp, c]
+        on_dev = 1 if rp.is_cuda else 0
+        if rp.is_cuda != c.is_cuda:
+            raise ValueError("row_ptr and col must live on the same device")
+        return Csr(rp.numel() - 1, c.numel(), rp.data_ptr(),
+                   c.data_ptr() if c.numel() else None, on_dev)
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    c = np.ascontiguousarray(col, dtype=np.int32)
+    keep.refs += [rp, c]
+    return Csr(len(rp) - 1, c.size, rp.ctypes.data, c.ctypes.data if c.size else None, 0)
+
+
+def make_opts(flags=0, budget=0, cache_rows=0, stream=None, tri_wave_max=0, c4_light_max=0) -> Opts:
+    o = Opts()
+    o.device_budget_bytes = int(budget)
+    o.flags = int(flags)
+    o.cache_rows = int(cache_rows)
+    o.hip_stream = stream
+    o.tri_wave_max = int(tri_wave_max)
+    o.c4_light_max = int(c4_light_max)
+    return o
+
+
+class Context:
+    """One device, one stream, a growable workspace (reused across calls)."""
+
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p()
+        rc = lib().m4_ctx_create(device, ctypes.byref(h))
+        if rc != M4_OK:
+            raise M4Error(rc, "m4_ctx_create: " + lib().m4_strerror(rc).decode())
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().m4_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != M4_OK:
+            raise M4Error(rc, lib().m4_last_error(self.h).decode())
+
+    @staticmethod
+    def _stream_for(x, stream):
+        if stream is not None:
+            return stream
+        if _is_torch(x) and x.is_cuda:
+            import torch
+            return torch.cuda.current_stream(x.device).cuda_stream
+        return None
+
+    def count(self, row_ptr, col, *, flags=0, budget=0, cache_rows=0, stream=None,
+              tri_wave_max=0, c4_light_max=0, stats=False, timing=False):
+        """Six counts; with stats=True (work counters) or timing=True (per
+        kernel HIP-event times) also the m4_stats dict."""
+        keep = _Keep()
+        g = make_csr(row_ptr, col, keep)
+        fl = flags | (M4_STATS if stats else 0) | (M4_TIMING if timing else 0)
+        o = make_opts(fl, budget, cache_rows, self._stream_for(row_ptr, stream), tri_wave_max,
+                      c4_light_max)
+        out = (ctypes.c_uint64 * 6)()
+        st = Stats()
+        self._check(lib().m4_count_motifs4_ex(self.h, ctypes.byref(g), ctypes.byref(o),
+                                              out, ctypes.byref(st)))
+        counts = tuple(int(x) for x in out)
+        return (counts, st.to_dict()) if (stats or timing) else counts
+
+    def edge_triangles(self, row_ptr, col, *, flags=0, stream=None, tri_wave_max=0):
+        """t_e for every CSR entry, in the input layout (numpy uint32 for host
+        inputs, a torch int32 tensor holding uint32 bits for device inputs)."""
+        keep = _Keep()
+        g = make_csr(row_ptr, col, keep)
+        o = make_opts(flags, 0, 0, self._stream_for(row_ptr, stream), tri_wave_max, 0)
+        if g.on_device:
+            import torch
+            t = torch.empty(max(g.nnz, 1), dtype=torch.int32, device=row_ptr.device)
+            ptr = t.data_ptr()
+        else:
+            t = np.zeros(max(g.nnz, 1), dtype=np.uint32)
+            ptr = t.ctypes.data
+        self._check(lib().m4_edge_triangles(self.h, ctypes.byref(g), ctypes.byref(o), ptr))
+        return t[: g.nnz]
+
+    def count_batch(self, voff, eoff, row_ptr, col, *, flags=0, stream=None, stats=False,
+                    tri_wave_max=0, c4_light_max=0):
+        """Counts of every graph of a packed arena (see m4_batch in m4.h);
+        returns a (G, 6) uint64 numpy array."""
+        keep = _Keep()
+        G = len(voff) - 1
+        if _is_torch(row_ptr):
+            import torch
+            arrs = [voff.to(torch.int64).contiguous(), eoff.to(torch.int64).contiguous(),
+                    row_ptr.to(torch.int64).contiguous(), col.to(torch.int32).contiguous()]
+            keep.refs += arrs
+            ptrs = [a.data_ptr() for a in arrs]
+            on_dev = 1 if row_ptr.is_cuda else 0
+        else:
+            arrs = [np.ascontiguousarray(voff, dtype=np.int64),
+                    np.ascontiguousarray(eoff, dtype=np.int64),
+                    np.ascontiguousarray(row_ptr, dtype=np.int64),
+                    np.ascontiguousarray(col, dtype=np.int32)]
+            if arrs[3].size == 0:
+                arrs[3] = np.zeros(1, dtype=np.int32)
+            keep.refs += arrs
+            ptrs = [a.ctypes.data for a in arrs]
+            on_dev = 0
+        b = Batch(G, *ptrs, on_dev)
+        o = make_opts(flags | (M4_STATS if stats else 0), 0, 0,
+                      self._stream_for(row_ptr, stream), tri_wave_max, c4_light_max)
+        out = np.zeros((max(G, 1), 6), dtype=np.uint64)
+        st = Stats()
+        self._check(lib().m4_count_batch(self.h, ctypes.byref(b), ctypes.byref(o),
+                                         out.ctypes.data, ctypes.byref(st)))
+        return (out[:G], st.to_dict()) if stats else out[:G]
+
+
+_default = None
+
+
+def default_context() -> Context:
+    global _default
+    if _default is None:
+        _default = Context(0)
+    return _default
+
+
+def count_motifs4(row_ptr, col, **kw):
+    """Six induced 4-node motif counts of one graph on GPU 0."""
+    return default_context().count(row_ptr, col, **kw)
+
+
+def pack_batch(graphs):
+    """Arena layout of m4_batch from a list of (row_ptr, col) host CSRs."""
+    G = len(graphs)
+    ns = np.array([len(rp) - 1 for rp, _ in graphs], dtype=np.int64)
+    ms = np.array([len(c) for _, c in graphs], dtype=np.int64)
+    voff = np.zeros(G + 1, dtype=np.int64)
+    eoff = np.zeros(G + 1, dtype=np.int64)
+    voff[1:] = np.cumsum(ns)
+    eoff[1:] = np.cumsum(ms)
+    row_ptr = np.concatenate([np.asarray(rp, dtype=np.int64) for rp, _ in graphs]) if G else \
+        np.zeros(0, dtype=np.int64)
+    col = np.concatenate([np.asarray(c, dtype=np.int32) for _, c in graphs]) if G else \
+        np.zeros(0, dtype=np.int32)
+    return voff, eoff, row_ptr, col

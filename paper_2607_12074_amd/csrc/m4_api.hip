@@ -1,0 +1,420 @@
+// m4_api.hip -- C ABI of the motif-count library: contexts, workspace and the
+// single-graph pipeline (CSR builder -> triangle/4-clique anchors -> 4-cycle
+// anchor -> closure -> exact inverse).
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <string>
+
+#include "m4_device.h"
+#include "m4_ctx.h"
+
+using namespace m4;
+
+// ----------------------------------------------------------------- context
+
+namespace m4 {
+
+void DevBuf::ensure(size_t bytes, hipStream_t s) {
+  if (bytes <= cap) return;
+  if (ptr) {
+    M4_HIP(hipStreamSynchronize(s));
+    M4_HIP(hipFree(ptr));
+    ptr = nullptr;
+    cap = 0;
+  }
+  size_t want = bytes + bytes / 8 + (1 << 20);
+  hipError_t e = hipMalloc((void**)&ptr, want);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    e = hipMalloc((void**)&ptr, bytes);
+    want = bytes;
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    ptr = nullptr;
+    throw Fail(M4_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+  cap = want;
+}
+
+void DevBuf::release() {
+  if (ptr) (void)hipFree(ptr);
+  ptr = nullptr;
+  cap = 0;
+}
+
+static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+size_t prep_bytes(int64_t n, int64_t nnz) {
+  size_t b = 0;
+  b += 5 * align256((size_t)n * 4 + 4);
+  b += 2 * align256((size_t)(n + 1) * 8);
+  b += align256((size_t)nnz * 4 + 4);
+  b += align256((size_t)(nnz / 2) * 4 + 4);
+  return b + 4096;
+}
+
+Prep carve_prep(char* base, int64_t n, int64_t nnz) {
+  Arena a;
+  a.base = base;
+  a.cap = prep_bytes(n, nnz);
+  Prep P;
+  P.perm = a.take<int32_t>(n + 1);
+  P.rank = a.take<int32_t>(n + 1);
+  P.dr = a.take<int32_t>(n + 1);
+  P.dlo = a.take<int32_t>(n + 1);
+  P.dplus = a.take<int32_t>(n + 1);
+  P.nptr = a.take<int64_t>(n + 1);
+  P.optr = a.take<int64_t>(n + 1);
+  P.ncol = a.take<int32_t>(nnz + 1);
+  P.t = a.take<uint32_t>(nnz / 2 + 1);
+  return P;
+}
+
+size_t stage_tmp_bytes(int64_t n, int64_t nnz, int64_t dmax, int num_cu) {
+  size_t build = build_tmp_bytes(n, nnz);
+  size_t tri = 2 * align256((size_t)n * 4 + 4) + align256(radix_tmp_elems(n, 4) * 8) + 4096;
+  size_t c4 = align256((size_t)n * 8 + 8) + 2 * align256((size_t)n * 4 + 4) +
+              align256(radix_tmp_elems(n, 2) * 8) + 4096 +
+              2 * align256((size_t)std::max<int64_t>(dmax, 1) * 4 * num_cu);
+  return std::max(build, std::max(tri, c4)) + (1 << 16);
+}
+
+int set_error(m4_ctx* ctx, int code, const std::string& msg) {
+  if (ctx) ctx->last_error = msg;
+  return code;
+}
+
+}  // namespace m4
+
+extern "C" int m4_ctx_create(int device, m4_ctx** out) {
+  if (!out) return M4_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+    (void)hipGetLastError();
+    return M4_EDEVICE;
+  }
+  m4_ctx* c = new (std::nothrow) m4_ctx();
+  if (!c) return M4_ENOMEM;
+  c->device = device;
+  try {
+    M4_HIP(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    M4_HIP(hipGetDeviceProperties(&prop, device));
+    c->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    c->arch = prop.gcnArchName;
+    M4_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    M4_HIP(hipMalloc((void**)&c->scal, sizeof(Scal)));
+    M4_HIP(hipHostMalloc((void**)&c->scal_host, sizeof(Scal), hipHostMallocDefault));
+    for (int i = 0; i < kNumEvents; i++) M4_HIP(hipEventCreate(&c->ev[i]));
+    for (int k = 0; k < M4_NK; k++)
+      for (int j = 0; j < 2; j++) M4_HIP(hipEventCreate(&c->ktimer.ev[k][j]));
+  } catch (const HipFail& f) {
+    (void)hipGetLastError();
+    m4_ctx_destroy(c);
+    return M4_EDEVICE;
+  }
+  *out = c;
+  return M4_OK;
+}
+
+extern "C" void m4_ctx_destroy(m4_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  c->prep.release();
+  c->tmp.release();
+  c->big.release();
+  c->input.release();
+  c->tout.release();
+  c->extra.release();
+  if (c->scal) (void)hipFree(c->scal);
+  if (c->scal_host) (void)hipHostFree(c->scal_host);
+  for (int i = 0; i < kNumEvents; i++)
+    if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+  for (int k = 0; k < M4_NK; k++)
+    for (int j = 0; j < 2; j++)
+      if (c->ktimer.ev[k][j]) (void)hipEventDestroy(c->ktimer.ev[k][j]);
+  if (c->stream) (void)hipStreamDestroy(c->stream);
+  destroy_ctx_extras(c);
+  delete c;
+}
+
+extern "C" const char* m4_last_error(const m4_ctx* c) {
+  return c ? c->last_error.c_str() : "no context";
+}
+
+extern "C" const char* m4_strerror(int st) {
+  switch (st) {
+    case M4_OK: return "ok";
+    case M4_EINVAL: return "invalid argument or malformed CSR";
+    case M4_ERANGE: return "size out of range (n or nnz >= 2^31, or nnz != row_ptr[n])";
+    case M4_EOVERFLOW: return "a count does not fit in 64 bits";
+    case M4_ENOMEM: return "out of memory or device budget too small";
+    case M4_EDEVICE: return "HIP device error";
+    case M4_EBUSY: return "queue full";
+    case M4_EINTERNAL: return "internal consistency check failed";
+    default: return "unknown status";
+  }
+}
+
+namespace m4 {
+
+int check_csr_args(const m4_csr* g) {
+  if (!g) return M4_EINVAL;
+  if (g->n < 0 || g->nnz < 0) return M4_EINVAL;
+  if (g->n >= (int64_t(1) << 31) || g->nnz >= (int64_t(1) << 31)) return M4_ERANGE;
+  if (g->nnz % 2) return M4_EINVAL;
+  if (!g->row_ptr) return M4_EINVAL;
+  if (g->nnz > 0 && !g->col) return M4_EINVAL;
+  return M4_OK;
+}
+
+// Brings the CSR to the device (copying host arrays into the context's input
+// buffer) and returns device pointers.
+void stage_input(m4_ctx* c, const m4_csr* g, hipStream_t s, const int64_t** rp,
+                 const int32_t** col, double* h2d_bytes) {
+  if (g->on_device) {
+    *rp = g->row_ptr;
+    *col = g->col;
+    return;
+  }
+  size_t rb = align256((size_t)(g->n + 1) * 8), cb = (size_t)g->nnz * 4 + 4;
+  c->input.ensure(rb + cb, s);
+  int64_t* drp = reinterpret_cast<int64_t*>(c->input.ptr);
+  int32_t* dcol = reinterpret_cast<int32_t*>(c->input.ptr + rb);
+  M4_HIP(hipMemcpyAsync(drp, g->row_ptr, (size_t)(g->n + 1) * 8, hipMemcpyHostToDevice, s));
+  if (g->nnz)
+    M4_HIP(hipMemcpyAsync(dcol, g->col, (size_t)g->nnz * 4, hipMemcpyHostToDevice, s));
+  if (h2d_bytes) *h2d_bytes += (double)((g->n + 1) * 8 + g->nnz * 4);
+  *rp = drp;
+  *col = dcol;
+}
+
+Tuning tuning_for(const m4_ctx* c, const m4_opts* o) {
+  Tuning tu = c->tune;
+  if (o && o->tri_wave_max > 0) tu.tri_wave_max = o->tri_wave_max;
+  if (o && o->c4_light_max > 0) tu.c4_light_max = o->c4_light_max;
+  // the hash bucket's table holds C4_HASH_SLOTS keys at load <= 1/2
+  tu.c4_light_max = std::max(0, std::min(tu.c4_light_max, C4_HASH_SLOTS / 2));
+  return tu;
+}
+
+// The resident single-graph pipeline.  Leaves the prepared graph in c->prep
+// (P) and the results in c->scal; the caller reads them back.
+void run_resident(m4_ctx* c, const int64_t* rp, const int32_t* col, int64_t n, int64_t nnz,
+                  const m4_opts* o, hipStream_t s, Prep& P, bool want_timing) {
+  KTimer* kt = nullptr;
+  if (o && (o->flags & M4_TIMING)) {
+    kt = &c->ktimer;
+    kt->on = true;
+    for (int i = 0; i < M4_NK; i++) kt->used[i] = false;
+  }
+  const uint32_t flags = o ? o->flags : 0;
+  const uint32_t cache_rows = o ? o->cache_rows : 0;
+  const Tuning tu = tuning_for(c, o);
+  c->prep.ensure(prep_bytes(n, nnz), s);
+  P = carve_prep(c->prep.ptr, n, nnz);
+  fill_u32(c->scal, 0, sizeof(Scal) / 4, s);
+  if (nnz / 2) fill_u32(P.t, 0, (size_t)(nnz / 2), s);
+  if (want_timing) M4_HIP(hipEventRecord(c->ev[0], s));
+  c->tmp.ensure(stage_tmp_bytes(n, nnz, 1, c->num_cu), s);
+  Arena a;
+  a.base = c->tmp.ptr;
+  a.cap = c->tmp.cap;
+  Classes C{};
+  if (kt) kt->begin(M4_K_BUILD, s);
+  build_prep(rp, col, n, nnz, (flags & M4_VALIDATE) != 0, P, C, c->scal, c->scal_host, a, s);
+  if (kt) kt->end(M4_K_BUILD, s);
+  if (want_timing) M4_HIP(hipEventRecord(c->ev[1], s));
+  auto big = [c, s](size_t bytes) -> char* {
+    c->big.ensure(bytes, s);
+    return c->big.ptr;
+  };
+  a.used = 0;
+  tri_run(P, c->scal, tu, flags, cache_rows, a, s, c->num_cu, big, kt);
+  if (want_timing) M4_HIP(hipEventRecord(c->ev[2], s));
+  c->tmp.ensure(stage_tmp_bytes(n, nnz, C.dmax, c->num_cu), s);
+  a.base = c->tmp.ptr;
+  a.cap = c->tmp.cap;
+  a.used = 0;
+  c4_run(P, C, c->scal, tu, flags, a, s, c->num_cu, kt);
+  if (want_timing) M4_HIP(hipEventRecord(c->ev[3], s));
+  if (kt) kt->begin(M4_K_CLOSURE, s);
+  closure_run(P, c->scal, flags, s);
+  finalize_run(c->scal, s);
+  if (kt) kt->end(M4_K_CLOSURE, s);
+  if (want_timing) M4_HIP(hipEventRecord(c->ev[4], s));
+}
+
+void fill_stats(m4_ctx* c, const Scal& h, m4_stats* st, bool timing) {
+  if (!st) return;
+  for (int i = 0; i < 8; i++) st->basis[i] = h.basis[i];
+  st->intersect_steps = h.stat[ST_STEPS];
+  st->wedges = h.stat[ST_WEDGES];
+  st->cache_lookups = h.stat[ST_LOOKUPS];
+  st->cache_hits = h.stat[ST_HITS];
+  for (int k = 0; k < M4_NK; k++) {
+    st->k_elems[k] = h.kstat[k][0];
+    st->k_rows[k] = h.kstat[k][1];
+    st->k_aux[k] = h.kstat[k][2];
+    st->k_aux2[k] = h.kstat[k][3];
+  }
+  if (c->ktimer.on) {
+    for (int k = 0; k < M4_NK; k++) {
+      float ms = 0;
+      if (c->ktimer.used[k] &&
+          hipEventElapsedTime(&ms, c->ktimer.ev[k][0], c->ktimer.ev[k][1]) == hipSuccess)
+        st->ms_kernel[k] = ms;
+    }
+    c->ktimer.on = false;
+  }
+  if (timing) {
+    float ms[4] = {0, 0, 0, 0};
+    for (int i = 0; i < 4; i++) (void)hipEventElapsedTime(&ms[i], c->ev[i], c->ev[i + 1]);
+    st->ms_build = ms[0];
+    st->ms_tri = ms[1];
+    st->ms_c4 = ms[2];
+    st->ms_closure = ms[3];
+  }
+}
+
+}  // namespace m4
+
+#define M4_GUARD_BEGIN try {
+#define M4_GUARD_END                                                                      \
+  }                                                                                       \
+  catch (const HipFail& f) {                                                              \
+    char buf[512];                                                                        \
+    snprintf(buf, sizeof(buf), "%s failed: %s (%s:%d)", f.what, hipGetErrorString(f.e),   \
+             f.file, f.line);                                                             \
+    (void)hipGetLastError();                                                              \
+    return set_error(ctx, M4_EDEVICE, buf);                                               \
+  }                                                                                       \
+  catch (const Fail& f) {                                                                 \
+    return set_error(ctx, f.code, f.msg);                                                 \
+  }                                                                                       \
+  catch (const std::bad_alloc&) {                                                         \
+    return set_error(ctx, M4_ENOMEM, "host allocation failed");                           \
+  }                                                                                       \
+  catch (...) {                                                                           \
+    return set_error(ctx, M4_EINTERNAL, "unexpected exception");                          \
+  }
+
+extern "C" int m4_count_motifs4_ex(m4_ctx* ctx, const m4_csr* g, const m4_opts* o,
+                                   uint64_t out[6], m4_stats* st) {
+  if (!ctx || !out) return M4_EINVAL;
+  int rc = check_csr_args(g);
+  if (rc) return set_error(ctx, rc, "bad CSR arguments");
+  M4_GUARD_BEGIN
+  M4_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = (o && o->hip_stream) ? (hipStream_t)o->hip_stream : ctx->stream;
+  const bool timing = st && o && (o->flags & (M4_STATS | M4_TIMING));
+  if (st) memset(st, 0, sizeof(*st));
+  if (g->n < 4 || g->nnz == 0) {
+    for (int i = 0; i < 6; i++) out[i] = 0;
+    if (st) st->partitions = 1;
+    return M4_OK;
+  }
+  if (needs_partition(ctx, g, o)) return count_partitioned(ctx, g, o, out, st);
+  double h2d = 0;
+  if (timing) M4_HIP(hipEventRecord(ctx->ev[5], s));
+  const int64_t* rp;
+  const int32_t* col;
+  stage_input(ctx, g, s, &rp, &col, &h2d);
+  if (!g->on_device) {
+    // row_ptr[n] must equal nnz
+    int64_t last = 0;
+    M4_HIP(hipMemcpyAsync(&last, rp + g->n, 8, hipMemcpyDeviceToHost, s));
+    M4_HIP(hipStreamSynchronize(s));
+    if (last != g->nnz) return set_error(ctx, M4_ERANGE, "row_ptr[n] != nnz");
+  }
+  if (timing) M4_HIP(hipEventRecord(ctx->ev[6], s));
+  Prep P;
+  run_resident(ctx, rp, col, g->n, g->nnz, o, s, P, timing);
+  M4_HIP(hipMemcpyAsync(ctx->scal_host, ctx->scal, sizeof(Scal), hipMemcpyDeviceToHost, s));
+  M4_HIP(hipStreamSynchronize(s));
+  const Scal& h = *ctx->scal_host;
+  if (h.err) return set_error(ctx, M4_EINVAL, "CSR is not simple, symmetric and sorted");
+  if (h.status == 3) return set_error(ctx, M4_EOVERFLOW, "a count is >= 2^64");
+  if (h.status != 0) return set_error(ctx, M4_EINTERNAL, "closure consistency check failed");
+  for (int i = 0; i < 6; i++) out[i] = h.out[i];
+  if (st) {
+    fill_stats(ctx, h, st, timing);
+    st->k_elems[M4_K_BUILD] = (uint64_t)g->nnz;
+    st->k_rows[M4_K_BUILD] = (uint64_t)g->n;
+    st->k_elems[M4_K_CLOSURE] = (uint64_t)(g->nnz / 2);
+    st->k_rows[M4_K_CLOSURE] = (uint64_t)g->n;
+    st->partitions = 1;
+    st->h2d_bytes = (uint64_t)h2d;
+    if (timing) {
+      float ms = 0, mh = 0;
+      (void)hipEventElapsedTime(&ms, ctx->ev[5], ctx->ev[4]);
+      (void)hipEventElapsedTime(&mh, ctx->ev[5], ctx->ev[6]);
+      st->ms_total = ms;
+      st->ms_h2d = mh;
+    }
+  }
+  return M4_OK;
+  M4_GUARD_END
+}
+
+extern "C" int m4_edge_triangles(m4_ctx* ctx, const m4_csr* g, const m4_opts* o, uint32_t* t_out) {
+  if (!ctx || !t_out) return M4_EINVAL;
+  int rc = check_csr_args(g);
+  if (rc) return set_error(ctx, rc, "bad CSR arguments");
+  M4_GUARD_BEGIN
+  M4_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = (o && o->hip_stream) ? (hipStream_t)o->hip_stream : ctx->stream;
+  if (g->nnz == 0) return M4_OK;
+  const int64_t* rp;
+  const int32_t* col;
+  stage_input(ctx, g, s, &rp, &col, nullptr);
+  Prep P;
+  const uint32_t flags = o ? o->flags : 0;
+  const Tuning tu = tuning_for(ctx, o);
+  ctx->prep.ensure(prep_bytes(g->n, g->nnz), s);
+  P = carve_prep(ctx->prep.ptr, g->n, g->nnz);
+  fill_u32(ctx->scal, 0, sizeof(Scal) / 4, s);
+  fill_u32(P.t, 0, (size_t)(g->nnz / 2), s);
+  ctx->tmp.ensure(stage_tmp_bytes(g->n, g->nnz, 1, ctx->num_cu), s);
+  Arena a;
+  a.base = ctx->tmp.ptr;
+  a.cap = ctx->tmp.cap;
+  Classes C{};
+  build_prep(rp, col, g->n, g->nnz, (flags & M4_VALIDATE) != 0, P, C, ctx->scal, ctx->scal_host,
+             a, s);
+  a.used = 0;
+  auto big = [ctx, s](size_t bytes) -> char* {
+    ctx->big.ensure(bytes, s);
+    return ctx->big.ptr;
+  };
+  tri_run(P, ctx->scal, tu, flags, o ? o->cache_rows : 0, a, s, ctx->num_cu, big, nullptr);
+  uint32_t* dst = t_out;
+  if (!g->on_device) {
+    ctx->tout.ensure((size_t)g->nnz * 4, s);
+    dst = reinterpret_cast<uint32_t*>(ctx->tout.ptr);
+  }
+  edge_t_to_input(P, rp, col, dst, s);
+  if (!g->on_device)
+    M4_HIP(hipMemcpyAsync(t_out, dst, (size_t)g->nnz * 4, hipMemcpyDeviceToHost, s));
+  M4_HIP(hipStreamSynchronize(s));
+  return M4_OK;
+  M4_GUARD_END
+}
+
+static std::once_flag g_default_once;
+static m4_ctx* g_default = nullptr;
+static int g_default_rc = M4_OK;
+static std::mutex g_default_mu;
+
+extern "C" int m4_count_motifs4(const m4_csr* g, uint64_t out[6]) {
+  std::call_once(g_default_once, [] { g_default_rc = m4_ctx_create(0, &g_default); });
+  if (g_default_rc != M4_OK) return g_default_rc;
+  std::lock_guard<std::mutex> lk(g_default_mu);
+  return m4_count_motifs4_ex(g_default, g, nullptr, out, nullptr);
+}

@@ -1,0 +1,53 @@
+// m4_ctx.h -- the context object behind the C ABI.
+#pragma once
+#include <string>
+
+#include "m4_internal.h"
+
+namespace m4 {
+
+// Growable device buffer owned by a context.
+struct DevBuf {
+  char* ptr = nullptr;
+  size_t cap = 0;
+  void ensure(size_t bytes, hipStream_t s);
+  void release();
+};
+
+constexpr int kNumEvents = 8;
+
+struct BatchState;
+struct PartState;
+
+size_t prep_bytes(int64_t n, int64_t nnz);
+Prep carve_prep(char* base, int64_t n, int64_t nnz);
+size_t stage_tmp_bytes(int64_t n, int64_t nnz, int64_t dmax, int num_cu);
+int set_error(m4_ctx* ctx, int code, const std::string& msg);
+int check_csr_args(const m4_csr* g);
+Tuning tuning_for(const m4_ctx* c, const m4_opts* o);
+void run_resident(m4_ctx* c, const int64_t* rp, const int32_t* col, int64_t n, int64_t nnz,
+                  const m4_opts* o, hipStream_t s, Prep& P, bool want_timing);
+
+// m4_part.hip
+bool needs_partition(m4_ctx* c, const m4_csr* g, const m4_opts* o);
+int count_partitioned(m4_ctx* c, const m4_csr* g, const m4_opts* o, uint64_t out[6],
+                      m4_stats* st);
+void destroy_ctx_extras(m4_ctx* c);
+
+}  // namespace m4
+
+struct m4_ctx {
+  int device = 0;
+  int num_cu = 256;
+  std::string arch;
+  hipStream_t stream = nullptr;
+  m4::Scal* scal = nullptr;       // device
+  m4::Scal* scal_host = nullptr;  // pinned
+  m4::DevBuf prep, tmp, big, input, tout, extra;
+  hipEvent_t ev[m4::kNumEvents] = {};
+  m4::KTimer ktimer;
+  m4::Tuning tune;
+  std::string last_error;
+  m4::BatchState* batch = nullptr;
+  m4::PartState* part = nullptr;
+};

@@ -1,0 +1,182 @@
+// m4_internal.h -- shared declarations of the MI355X motif-count library.
+// Device arrays of a graph prepared in "rank space": vertices are relabelled
+// by the degree order (d, id) (the canonical order of Section III-D), every
+// row is sorted, and the oriented out-list N+(r) of vertex r is the suffix of
+// its row holding the neighbours of higher rank.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <functional>
+#include <string>
+
+#include "../../include/m4.h"
+
+namespace m4 {
+
+constexpr int WAVE = 64;
+
+// 128-bit unsigned accumulator in device memory, added to with two 64-bit
+// atomics (exact: the carry of the low word is derived from its own old value).
+struct U128 {
+  unsigned long long lo, hi;
+};
+
+enum Acc { ACC_K4 = 0, ACC_C4, ACC_S, ACC_P, ACC_PAW2, ACC_D, ACC_SUMT, ACC_N };
+enum Stat { ST_STEPS = 0, ST_WEDGES, ST_LOOKUPS, ST_HITS, ST_N = 8 };
+
+// Triangle-owner buckets by out-degree k = d+(u).
+enum TriBucket { TB_NONE = 0, TB_WAVE, TB_LDS, TB_GLOBAL, TB_N = 4 };
+// 4-cycle-owner buckets by wedge bound.
+enum C4Bucket { CB_NONE = 0, CB_HASH, CB_WIN16, CB_WIN32, CB_N = 4 };
+
+// Largest out-degree handled with the bitmap rows in LDS.
+constexpr int TRI_LDS_MAX = 1024;
+// 4-cycle window widths (16-bit and 32-bit counters, 128 KiB of LDS).
+constexpr int C4_WIN16 = 65536;
+constexpr int C4_WIN32 = 32768;
+constexpr int C4_HASH_SLOTS = 4096;
+
+struct Scal {
+  U128 acc[ACC_N + 1];
+  unsigned long long stat[ST_N];
+  unsigned int dmax;
+  int err;
+  unsigned int work[8];
+  int64_t tri_start[TB_N + 1];
+  int64_t c4_start[CB_N + 1];
+  unsigned long long out[6];
+  unsigned long long basis[8];  // T, K4, C4_ni, S, P_ni, Paw_ni, D_ni, sum_t
+  unsigned long long kstat[M4_NK][4];  // per kernel slot: elems, rows, aux, aux2
+  int status;
+  int pad;
+};
+
+struct Prep {
+  int64_t n = 0, nnz = 0, m = 0;
+  int32_t* perm = nullptr;  // rank -> input id
+  int32_t* rank = nullptr;  // input id -> rank
+  int32_t* dr = nullptr;    // degree by rank (non-decreasing)
+  int32_t* dlo = nullptr;   // neighbours of lower rank
+  int32_t* dplus = nullptr; // neighbours of higher rank = |N+(r)|
+  int64_t* nptr = nullptr;  // row offsets in rank space [n+1]
+  int64_t* optr = nullptr;  // oriented edge offsets [n+1]
+  int32_t* ncol = nullptr;  // rows in rank space, sorted [nnz]
+  uint32_t* t = nullptr;    // triangles per oriented edge [m]
+};
+
+// Rank boundaries of degree classes, read back once per graph.
+struct Classes {
+  int64_t r1;            // first rank with degree >= 2
+  int64_t bound[16];     // first rank with degree > thr[i]
+  int dmax;
+};
+
+// ------------------------------------------------------------ workspace
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+  template <typename T>
+  T* take(size_t count) {
+    size_t bytes = (count * sizeof(T) + 255) & ~size_t(255);
+    if (bytes == 0) bytes = 256;
+    if (used + bytes > cap) return nullptr;
+    T* p = reinterpret_cast<T*>(base + used);
+    used += bytes;
+    return p;
+  }
+};
+
+struct Tuning {
+  int tri_wave_max = 64;    // <= WAVE
+  int c4_light_max = 2048;  // wedge bound for the hash bucket
+  int grid_mult = 8;        // persistent blocks per CU for light kernels
+};
+
+// Optional per-launch HIP event pairs (M4_TIMING).
+struct KTimer {
+  bool on = false;
+  hipEvent_t ev[M4_NK][2] = {};
+  bool used[M4_NK] = {};
+  void begin(int k, hipStream_t s) {
+    if (on) {
+      (void)hipEventRecord(ev[k][0], s);
+      used[k] = true;
+    }
+  }
+  void end(int k, hipStream_t s) {
+    if (on) (void)hipEventRecord(ev[k][1], s);
+  }
+};
+
+// ------------------------------------------------------ launch helpers
+struct Err {
+  int code = M4_OK;
+  std::string msg;
+};
+
+#define M4_HIP(expr)                                                       \
+  do {                                                                     \
+    hipError_t e_ = (expr);                                                \
+    if (e_ != hipSuccess) {                                                \
+      throw ::m4::HipFail(e_, #expr, __FILE__, __LINE__);                  \
+    }                                                                      \
+  } while (0)
+
+struct HipFail {
+  hipError_t e;
+  const char* what;
+  const char* file;
+  int line;
+  HipFail(hipError_t e_, const char* w, const char* f, int l) : e(e_), what(w), file(f), line(l) {}
+};
+
+struct Fail {
+  int code;
+  std::string msg;
+  Fail(int c, std::string m) : code(c), msg(std::move(m)) {}
+};
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ------------------------------------------------- primitives (m4_prims)
+// Exclusive scan: out[0..count] with out[count] = total.  tmp must hold
+// scan_tmp_elems(count) int64.
+size_t scan_tmp_elems(int64_t count);
+void scan_i32(const int32_t* in, int64_t count, int64_t* out, int64_t* tmp, hipStream_t s);
+void scan_i64(const int64_t* in, int64_t count, int64_t* out, int64_t* tmp, hipStream_t s);
+
+// Stable partition of items [0, count) by a small key (bucket id < 2^bits),
+// and the general stable radix pass used by the degree sort.
+size_t radix_tmp_elems(int64_t count, int bits);
+void radix_pass(const uint32_t* keys_in, const int32_t* vals_in, int64_t count, int shift,
+                int bits, uint32_t* keys_out, int32_t* vals_out, int64_t* tmp,
+                int64_t* bucket_start /* nullable, [2^bits + 1] */, hipStream_t s);
+
+void fill_u32(void* p, uint32_t v, size_t count32, hipStream_t s);
+
+// --------------------------------------------------- stages (per file)
+// m4_build.hip
+size_t build_tmp_bytes(int64_t n, int64_t nnz);
+void build_prep(const int64_t* rp, const int32_t* col, int64_t n, int64_t nnz, bool validate,
+                Prep& P, Classes& C, Scal* scal, Scal* scal_host, Arena& tmp, hipStream_t s);
+void edge_t_to_input(const Prep& P, const int64_t* rp, const int32_t* col, uint32_t* t_out,
+                     hipStream_t s);
+
+// m4_tri.hip
+size_t tri_tmp_bytes(int64_t n, int64_t nnz, int dplus_max_bound);
+// big_scratch(bytes) returns device memory for owners whose bitmap does not
+// fit in LDS (only called when such owners exist).
+void tri_run(const Prep& P, Scal* scal, const Tuning& tu, uint32_t flags, uint32_t cache_rows,
+             Arena& tmp, hipStream_t s, int num_cu,
+             const std::function<char*(size_t)>& big_scratch, KTimer* kt);
+
+// m4_c4.hip
+void c4_run(const Prep& P, const Classes& C, Scal* scal, const Tuning& tu, uint32_t flags,
+            Arena& tmp, hipStream_t s, int num_cu, KTimer* kt);
+
+// m4_closure.hip
+void closure_run(const Prep& P, Scal* scal, uint32_t flags, hipStream_t s);
+void finalize_run(Scal* scal, hipStream_t s);
+
+}  // namespace m4

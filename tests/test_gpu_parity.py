@@ -1,0 +1,173 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle,
+bit-exact on every count and on every per-edge triangle count."""
+import json
+import os
+from math import comb
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+from tests import graphs as G
+from tests.test_oracle_pins import CLOSED, cf_wheel
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2607_12074_amd as m4
+    c = m4.Context(0)
+    yield c
+    c.close()
+
+
+def test_closed_forms(ctx):
+    for name, make, exp in CLOSED:
+        assert ctx.count(*make()) == exp, name
+
+
+def cocktail_party(k):
+    # K_{2,2,...,2} with k parts: a 4-set holding 2 antipodal pairs is a
+    # 4-cycle, 1 pair a diamond, none a 4-clique
+    n = 2 * k
+    edges = [(a, b) for a in range(n) for b in range(a + 1, n) if b != a + k]
+    return G.csr(n, edges), (0, 0, 0, comb(k, 2), 4 * k * comb(k - 1, 2), 16 * comb(k, 4))
+
+
+def test_dense_out_lists_global_bitmap(ctx):
+    # out-degrees above 1024 take the bitmap-in-global-memory owners
+    g, exp = cocktail_party(560)
+    assert ctx.count(*g) == exp
+    assert ctx.count(*G.complete(1050)) == (0, 0, 0, 0, 0, comb(1050, 4))
+
+
+def test_hub_rows_and_window_counters(ctx):
+    # a 40000-spoke wheel: the hub row is sorted by the bitmap kernel and the
+    # hub's 4-cycle owner uses the windowed counters
+    k = 40000
+    assert ctx.count(*G.wheel(k)) == cf_wheel(k)
+    assert ctx.count(*G.star(40000)) == (comb(40000, 3), 0, 0, 0, 0, 0)
+    g = G.complete_bipartite(3, 70000)
+    assert ctx.count(*g) == (3 * comb(70000, 3) + 70000 * comb(3, 3), 0, 0,
+                             comb(3, 2) * comb(70000, 2), 0, 0)
+
+
+def _random_cases():
+    out = []
+    for s in range(30):
+        n = 10 + (s * 37) % 300
+        p = 0.02 + 0.25 * ((s * 13) % 10) / 10
+        out.append(G.gnp(n, p, 100 + s))
+    for s in range(8):
+        out.append(gg.ba(200 + 50 * s, 2 + s, s))
+    for s in range(6):
+        out.append(G.planted_cliques(400, 2000, [30 + 10 * s, 12], s))
+    out.append(gg.rmat(12, 8, 0.57, 0.19, 0.19, 3))
+    out.append(gg.chunglu(5000, 2.2, 10.0, 4))
+    out.append(gg.rgg(5000, 10.0, 5))
+    return out
+
+
+def test_random_graphs_vs_oracle(ctx):
+    for i, g in enumerate(_random_cases()):
+        assert ctx.count(*g) == oracle.closure(*g), i
+
+
+def test_small_graphs_vs_brute_force(ctx):
+    for s in range(20):
+        g = G.gnp(9 + s % 12, 0.3, 900 + s)
+        assert ctx.count(*g) == oracle.brute(*g), s
+
+
+def test_er_workload_golden(ctx):
+    gold = json.load(open(os.path.join(HERE, "golden", "er_2000_20000.json")))
+    g = gg.er_c1(seed=1)
+    counts, st = ctx.count(*g, stats=True)
+    assert list(counts) == gold["counts"]
+    for k, v in gold["basis"].items():
+        assert st[k] == v, k
+
+
+def test_batch_golden_graphs_single(ctx):
+    gold = json.load(open(os.path.join(HERE, "golden", "batch_first64.json")))
+    for rec in gold["graphs"][:24]:
+        g = gg.batch_graph(rec["index"])
+        assert list(ctx.count(*g)) == rec["counts"], rec["index"]
+
+
+def test_edge_triangles_elementwise(ctx):
+    for g in (gg.er_c1(seed=1), gg.rmat(13, 10, 0.57, 0.19, 0.19, 7),
+              G.planted_cliques(600, 3000, [70, 25], 9)):
+        _, t_ref = oracle.closure(*g, want_t=True)
+        t = ctx.edge_triangles(*g)
+        assert np.array_equal(t, t_ref)
+
+
+def test_cache_modes_identical(ctx):
+    import paper_2607_12074_amd as m4
+    for g in (G.planted_cliques(500, 2500, [90, 40, 20], 3),
+              gg.rmat(13, 12, 0.57, 0.19, 0.19, 11)):
+        ref = oracle.closure(*g)
+        on, st_on = ctx.count(*g, stats=True)
+        off, st_off = ctx.count(*g, flags=m4.M4_NO_CACHE, stats=True)
+        tiny, st_tiny = ctx.count(*g, cache_rows=3, stats=True)
+        assert on == off == tiny == ref
+        assert st_on["cache_lookups"] == st_off["cache_lookups"] == st_tiny["cache_lookups"]
+        assert st_on["cache_hits"] == st_on["cache_lookups"] > 0
+        assert st_off["cache_hits"] == 0
+        assert 0 < st_tiny["cache_hits"] < st_tiny["cache_lookups"]
+
+
+def test_threshold_sweep_identical(ctx):
+    g = gg.rmat(14, 10, 0.57, 0.19, 0.19, 5)
+    ref = oracle.closure(*g)
+    for tw in (2, 5, 16, 64):
+        for cl in (1, 64, 2048):
+            assert ctx.count(*g, tri_wave_max=tw, c4_light_max=cl) == ref, (tw, cl)
+
+
+def test_device_tensor_input(ctx):
+    import torch
+    g = gg.rmat(12, 10, 0.57, 0.19, 0.19, 8)
+    rp = torch.from_numpy(g[0]).cuda()
+    col = torch.from_numpy(g[1]).cuda()
+    assert ctx.count(rp, col) == ctx.count(*g) == oracle.closure(*g)
+    t_dev = ctx.edge_triangles(rp, col).cpu().numpy().view(np.uint32)
+    assert np.array_equal(t_dev, ctx.edge_triangles(*g))
+
+
+def test_validation_rejects_malformed(ctx):
+    import paper_2607_12074_amd as m4
+    rp, col = G.gnp(40, 0.2, 1)
+    bad = col.copy()
+    bad[0], bad[1] = bad[1], bad[0]  # unsorted row
+    with pytest.raises(m4.M4Error) as e:
+        ctx.count(rp, bad, flags=m4.M4_VALIDATE)
+    assert e.value.code == m4.M4_EINVAL
+    # asymmetric: drop one direction of an edge
+    rp2, col2 = G.csr(4, [(0, 1), (1, 2), (2, 3)])
+    col3 = col2.copy()
+    col3[0] = 2  # 0 -> 2 without 2 -> 0
+    with pytest.raises(m4.M4Error):
+        ctx.count(rp2, col3, flags=m4.M4_VALIDATE)
+    assert ctx.count(rp, col, flags=m4.M4_VALIDATE) == oracle.closure(rp, col)
+    with pytest.raises(m4.M4Error) as e:
+        ctx.count(rp, col[:-2])
+    assert e.value.code == m4.M4_ERANGE
+
+
+def test_empty_and_tiny(ctx):
+    assert ctx.count(*G.csr(0, [])) == (0,) * 6
+    assert ctx.count(*G.csr(3, [(0, 1), (1, 2)])) == (0,) * 6
+    assert ctx.count(*G.csr(100, [])) == (0,) * 6
+    assert ctx.count(*G.csr(5, [(0, 1), (1, 2), (2, 3)])) == (0, 1, 0, 0, 0, 0)
+
+
+def test_repeat_is_deterministic(ctx):
+    g = gg.rmat(14, 12, 0.57, 0.19, 0.19, 13)
+    a = ctx.count(*g)
+    b = ctx.count(*g)
+    assert a == b == oracle.closure(*g)
