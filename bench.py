@@ -85,6 +85,107 @@ def traffic_for(kernel: str, digest: str):
     return ent.get("bytes_per_launch")
 
 
+def run_batch_leg(ctx, args):
+    """Uneven batch: graphs/s of the persistent fused launch (hipGraph replay)
+    against the plain one-graph-per-call loop, both on device-resident arenas
+    and on the same stream; every graph's counts must agree."""
+    import numpy as np
+    import torch
+    import graphgen as gg
+    import paper_2607_12074_amd as m4
+
+    G = args.batch_graphs
+    t0 = time.perf_counter()
+    graphs = [gg.batch_graph(i) for i in range(G)]
+    arena = m4.pack_batch(graphs)
+    gen_s = time.perf_counter() - t0
+    dev = [torch.from_numpy(a).cuda() for a in arena]
+    sum_m = int(arena[1][-1]) // 2
+    out = ctx.count_batch(*dev)  # plan + capture
+    for _ in range(2):
+        ctx.count_batch(*dev)
+    torch.cuda.synchronize()
+    steps = max(args.steps, 1)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = ctx.count_batch(*dev)
+    torch.cuda.synchronize()
+    ms_batch = (time.perf_counter() - t0) * 1e3 / steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain = ctx.count_batch(*dev, plain=True)
+    torch.cuda.synchronize()
+    ms_plain = (time.perf_counter() - t0) * 1e3
+    return {"workload": f"{G} graphs, n log-uniform in [20, 5000], even G(n, m) with mean "
+                        "degree U[3, 30], odd Barabasi-Albert m U{2..8}, seed 3",
+            "graphs": G, "sum_m": sum_m, "ms_per_batch": ms_batch,
+            "graphs_per_s": G / (ms_batch * 1e-3), "edges_per_s": sum_m / (ms_batch * 1e-3),
+            "plain_ms": ms_plain, "plain_graphs_per_s": G / (ms_plain * 1e-3),
+            "speedup_vs_plain": ms_plain / ms_batch,
+            "plain_equal": bool(np.array_equal(plain, out)), "gen_s": round(gen_s, 2)}
+
+
+def run_serve_leg(ctx, args):
+    """Serving: requests with n log-normal (median 5000, sigma 1.5, cap 2M),
+    half Chung-Lu power law, half random geometric.  First a closed loop
+    (everything submitted at once) gives the saturation rate; then a Poisson
+    stream at 0.7 of it is replayed and p50/p99 latency (done - submit) and
+    graphs/s are reported.  Both runs must return identical counts."""
+    import numpy as np
+    import graphgen as gg
+    import paper_2607_12074_amd as m4
+
+    R = args.serve_requests
+    t0 = time.perf_counter()
+    graphs = [gg.serve_graph(i) for i in range(R)]
+    gen_s = time.perf_counter() - t0
+    budget = int(args.serve_budget_gb * (1 << 30))
+
+    def collect(srv, ids):
+        got = {}
+        while len(got) < len(ids):
+            for r in srv.poll(1024):
+                got[r["id"]] = r
+            time.sleep(0.0002)
+        return [got[i] for i in ids]
+
+    srv = m4.Server(ctx, budget)
+    for g in graphs[: min(R, 32)]:  # warm the lanes
+        srv.submit(*g)
+    srv.drain()
+    srv.poll(1 << 16)
+    t0 = time.perf_counter()
+    ids = [srv.submit(*g, tag=i) for i, g in enumerate(graphs)]
+    closed = collect(srv, ids)
+    sat = R / (time.perf_counter() - t0)
+    rate = 0.7 * sat
+    gaps = np.random.default_rng(7).exponential(1.0 / rate, R)
+    ids = []
+    t_next = time.perf_counter()
+    for i, g in enumerate(graphs):
+        t_next += gaps[i]
+        while time.perf_counter() < t_next:
+            pass
+        ids.append(srv.submit(*g, tag=i))
+    opened = collect(srv, ids)
+    st = srv.stats()
+    srv.close()
+    lat = np.array([r["t_done_ms"] - r["t_submit_ms"] for r in opened])
+    span = max(r["t_done_ms"] for r in opened) - min(r["t_submit_ms"] for r in opened)
+    same = all(a["counts"] == b["counts"] and a["status"] == 0 == b["status"]
+               for a, b in zip(closed, opened))
+    ns = np.array([len(g[0]) - 1 for g in graphs])
+    return {"workload": f"{R} requests, n log-normal median 5000 sigma 1.5 cap 2M, even "
+                        "Chung-Lu exponent U[2.1,2.8], odd random geometric, mean degree "
+                        "U[6,12], seed 5",
+            "requests": R, "n_p50": int(np.median(ns)), "n_max": int(ns.max()),
+            "saturation_graphs_per_s": sat, "offered_rate": rate,
+            "graphs_per_s": R / (span * 1e-3), "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "budget_bytes": budget,
+            "max_inflight_bytes": st["max_inflight_bytes"], "launches": st["launches"],
+            "mix_equals_closed_loop": bool(same), "gen_s": round(gen_s, 2)}
+
+
 def make_workload(args):
     import graphgen as gg
     t0 = time.perf_counter()
@@ -102,6 +203,11 @@ def main():
     ap.add_argument("--edge-factor", type=int, default=10)
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--batch-graphs", type=int, default=4096,
+                    help="graphs of the uneven batch (0 = skip the batched leg)")
+    ap.add_argument("--serve-requests", type=int, default=600,
+                    help="requests of the serving leg (0 = skip it)")
+    ap.add_argument("--serve-budget-gb", type=float, default=32.0)
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (PMC calibration)")
     args = ap.parse_args()
@@ -171,6 +277,9 @@ def main():
                "sample": f"whole workload graph (n={n}, m={m}), plain closure counter, "
                          f"{cpu_s:.1f} s"}
 
+    batched = run_batch_leg(ctx, args) if args.batch_graphs > 0 else None
+    serving = run_serve_leg(ctx, args) if args.serve_requests > 0 else None
+
     line = {
         "metric": METRIC,
         "value": m / (ms_step * 1e-3),
@@ -193,12 +302,18 @@ def main():
         "roofline": {"bound": "hbm", "kernel": KERNEL_SYMBOL[dname], "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "alg_bytes": B, "ms": float(ms_k[dom])},
-        "kernels_ms": {names[i]: round(float(ms_k[i]), 4) for i in range(len(names))
-                       if ms_k[i] > 0},
+        "kernels": {names[i]: {"ms": round(float(ms_k[i]), 4), "elems": st["k_elems"][i],
+                               "rows": st["k_rows"][i], "aux": st["k_aux"][i],
+                               "aux2": st["k_aux2"][i],
+                               "GBps": round(alg_bytes(i, st, n, m) / (ms_k[i] * 1e6), 1)
+                               if ms_k[i] > 0 and i > 0 else None}
+                    for i in range(len(names)) if ms_k[i] > 0},
         "work": {"intersect_steps": st["intersect_steps"], "wedges": st["wedges"],
                  "cache_lookups": st["cache_lookups"], "cache_hits": st["cache_hits"],
                  "intersection_work_per_edge": (st["intersect_steps"] + st["wedges"]) / m},
         "cpu_baseline": cpu,
+        "batched": batched,
+        "serving": serving,
         "source_digest": digest,
         "gen_s": round(gen_s, 2),
     }

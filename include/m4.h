@@ -67,6 +67,8 @@ typedef struct {
 #define M4_FORCE_PARTITION 0x4u /* take the halo-partition path even if it fits      */
 #define M4_STATS 0x8u           /* fill the work counters of m4_stats               */
 #define M4_TIMING 0x10u         /* time every kernel launch with HIP events         */
+#define M4_PLAIN_LOOP 0x20u     /* m4_count_batch: one single-graph call per graph
+                                   (the reference point of the batched launch)     */
 
 typedef struct {
   uint64_t device_budget_bytes; /* 0 = no budget (whole device)                    */
@@ -192,6 +194,10 @@ int m4_server_drain(m4_server* s);
 void m4_server_destroy(m4_server* s);
 /* Milliseconds on the server clock (the clock of m4_result times). */
 double m4_server_now_ms(const m4_server* s);
+/* Largest device footprint admitted at once (never above the budget), number
+ * of fused launches and completed requests so far. */
+int m4_server_stats(const m4_server* s, uint64_t* max_inflight_bytes, uint64_t* launches,
+                    uint64_t* completed);
 
 #ifdef __cplusplus
 }

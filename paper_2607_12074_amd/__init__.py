@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(HERE, "libm4.so")
 
 M4_OK, M4_EINVAL, M4_ERANGE, M4_EOVERFLOW, M4_ENOMEM, M4_EDEVICE, M4_EBUSY, M4_EINTERNAL = range(8)
 M4_VALIDATE, M4_NO_CACHE, M4_FORCE_PARTITION, M4_STATS, M4_TIMING = 0x1, 0x2, 0x4, 0x8, 0x10
+M4_PLAIN_LOOP = 0x20
 M4_NK = 16
 KERNELS = ("build", "tri_global", "tri_1024", "tri_512", "tri_256", "tri_128", "tri_wave",
            "c4_plan", "c4_win16", "c4_win32", "c4_hash", "closure")
@@ -231,7 +232,7 @@ class Context:
         return t[: g.nnz]
 
     def count_batch(self, voff, eoff, row_ptr, col, *, flags=0, stream=None, stats=False,
-                    tri_wave_max=0, c4_light_max=0):
+                    tri_wave_max=0, c4_light_max=0, plain=False):
         """Counts of every graph of a packed arena (see m4_batch in m4.h);
         returns a (G, 6) uint64 numpy array."""
         keep = _Keep()
@@ -254,6 +255,8 @@ class Context:
             ptrs = [a.ctypes.data for a in arrs]
             on_dev = 0
         b = Batch(G, *ptrs, on_dev)
+        if plain:
+            flags |= M4_PLAIN_LOOP
         o = make_opts(flags | (M4_STATS if stats else 0), 0, 0,
                       self._stream_for(row_ptr, stream), tri_wave_max, c4_light_max)
         out = np.zeros((max(G, 1), 6), dtype=np.uint64)
@@ -292,3 +295,63 @@ def pack_batch(graphs):
     col = np.concatenate([np.asarray(c, dtype=np.int32) for _, c in graphs]) if G else \
         np.zeros(0, dtype=np.int32)
     return voff, eoff, row_ptr, col
+
+
+class Server:
+    """Continuous-batching request loop on one device (m4_server_* C ABI).
+
+    submit() copies a host CSR into the server and returns its id at once;
+    poll() returns finished requests as dicts with the six counts and the
+    submit / admit / done times (ms on the server clock)."""
+
+    def __init__(self, ctx: Context, hbm_budget_bytes: int, max_queue: int = 0):
+        L = lib()
+        L.m4_server_stats.argtypes = [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_uint64)] * 3
+        h = ctypes.c_void_p()
+        rc = L.m4_server_create(ctx.h, int(hbm_budget_bytes), int(max_queue), ctypes.byref(h))
+        if rc != M4_OK:
+            raise M4Error(rc, "m4_server_create: " + L.m4_strerror(rc).decode())
+        self.h = h
+        self.ctx = ctx
+
+    def submit(self, row_ptr, col, tag: int = 0) -> int:
+        keep = _Keep()
+        g = make_csr(row_ptr, col, keep)
+        rid = ctypes.c_uint64()
+        rc = lib().m4_server_submit(self.h, ctypes.byref(g), int(tag), ctypes.byref(rid))
+        if rc != M4_OK:
+            raise M4Error(rc, "m4_server_submit: " + lib().m4_strerror(rc).decode())
+        return rid.value
+
+    def poll(self, max_results: int = 1024):
+        res = (Result * max(max_results, 1))()
+        got = ctypes.c_int()
+        rc = lib().m4_server_poll(self.h, res, int(max_results), ctypes.byref(got))
+        if rc != M4_OK:
+            raise M4Error(rc, "m4_server_poll")
+        return [{"id": r.id, "tag": r.tag, "status": r.status,
+                 "counts": tuple(int(x) for x in r.counts), "t_submit_ms": r.t_submit_ms,
+                 "t_admit_ms": r.t_admit_ms, "t_done_ms": r.t_done_ms}
+                for r in res[: got.value]]
+
+    def drain(self):
+        lib().m4_server_drain(self.h)
+
+    def now_ms(self) -> float:
+        return lib().m4_server_now_ms(self.h)
+
+    def stats(self):
+        a, b, c = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        lib().m4_server_stats(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+        return {"max_inflight_bytes": a.value, "launches": b.value, "completed": c.value}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().m4_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

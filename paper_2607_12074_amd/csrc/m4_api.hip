@@ -77,9 +77,10 @@ Prep carve_prep(char* base, int64_t n, int64_t nnz) {
 size_t stage_tmp_bytes(int64_t n, int64_t nnz, int64_t dmax, int num_cu) {
   size_t build = build_tmp_bytes(n, nnz);
   size_t tri = 2 * align256((size_t)n * 4 + 4) + align256(radix_tmp_elems(n, 4) * 8) + 4096;
-  size_t c4 = align256((size_t)n * 8 + 8) + 2 * align256((size_t)n * 4 + 4) +
-              align256(radix_tmp_elems(n, 2) * 8) + 4096 +
-              2 * align256((size_t)std::max<int64_t>(dmax, 1) * 4 * num_cu);
+  (void)dmax;
+  (void)num_cu;
+  size_t c4 = 2 * align256((size_t)(n + 1) * 8 + 8) + 4 * align256((size_t)n * 4 + 4) +
+              align256(radix_tmp_elems(n, 2) * 8) + align256(scan_tmp_elems(n) * 8) + 4096;
   return std::max(build, std::max(tri, c4)) + (1 << 16);
 }
 
@@ -242,7 +243,7 @@ void run_resident(m4_ctx* c, const int64_t* rp, const int32_t* col, int64_t n, i
   a.base = c->tmp.ptr;
   a.cap = c->tmp.cap;
   a.used = 0;
-  c4_run(P, C, c->scal, tu, flags, a, s, c->num_cu, kt);
+  c4_run(P, C, c->scal, tu, flags, a, s, c->num_cu, kt, big);
   if (want_timing) M4_HIP(hipEventRecord(c->ev[3], s));
   if (kt) kt->begin(M4_K_CLOSURE, s);
   closure_run(P, c->scal, flags, s);

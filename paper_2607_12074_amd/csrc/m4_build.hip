@@ -25,12 +25,17 @@ __global__ void k_degree(const int64_t* __restrict__ rp, int64_t n, uint32_t* __
     d = (uint32_t)(rp[v + 1] - rp[v]);
     deg[v] = d;
   }
-  // wavefront max, one atomic per wavefront
+  // block max, one atomic per block
+  __shared__ uint32_t bmax;
+  if (threadIdx.x == 0) bmax = 0;
+  __syncthreads();
   for (int o = WAVE / 2; o > 0; o >>= 1) {
     uint32_t e = __shfl_xor(d, o, WAVE);
     d = d > e ? d : e;
   }
-  if ((threadIdx.x & (WAVE - 1)) == 0 && d) atomicMax(&scal->dmax, d);
+  if ((threadIdx.x & (WAVE - 1)) == 0 && d) atomicMax(&bmax, d);
+  __syncthreads();
+  if (threadIdx.x == 0 && bmax) atomicMax(&scal->dmax, bmax);
 }
 
 __device__ __forceinline__ int64_t row_of(const int64_t* __restrict__ rp, int64_t n, int64_t q) {
@@ -114,15 +119,18 @@ __global__ __launch_bounds__(256) void k_row_small(const int64_t* __restrict__ r
                                                    const int32_t* __restrict__ dr, int64_t r_lo,
                                                    int64_t r_hi, int32_t* __restrict__ ncol,
                                                    int32_t* __restrict__ dlo,
-                                                   int32_t* __restrict__ dplus) {
+                                                   int32_t* __restrict__ dplus, int64_t r_base) {
+  // r is the rank (compared with the relabelled neighbours); li = r - r_base
+  // indexes the per-row arrays, which may hold a chunk of rows only
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t r = r_lo + t / G;
   int j = (int)(t % G);
   bool rowok = r < r_hi;
-  int d = rowok ? dr[r] : 0;
+  const int64_t li = rowok ? r - r_base : 0;
+  int d = rowok ? dr[li] : 0;
   bool mine = rowok && j < d;
   int32_t x = INT_MAX;
-  if (mine) x = rank[col[rp[perm[r]] + j]];
+  if (mine) x = rank[col[rp[perm[li]] + j]];
   const int lane = threadIdx.x & (WAVE - 1);
   const int gbase = lane & ~(G - 1);
   int pos = 0;
@@ -133,11 +141,11 @@ __global__ __launch_bounds__(256) void k_row_small(const int64_t* __restrict__ r
   }
   uint64_t below = __ballot(mine && x < r);
   uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1) << gbase);
-  if (mine) ncol[nptr[r] + pos] = x;
+  if (mine) ncol[nptr[li] + pos] = x;
   if (rowok && j == 0) {
     int b = __popcll(below & gmask);
-    dlo[r] = b;
-    dplus[r] = d - b;
+    dlo[li] = b;
+    dplus[li] = d - b;
   }
 }
 
@@ -151,12 +159,12 @@ __global__ __launch_bounds__(NT) void k_row_bitonic(const int64_t* __restrict__ 
                                                     const int32_t* __restrict__ dr, int64_t r_lo,
                                                     int32_t* __restrict__ ncol,
                                                     int32_t* __restrict__ dlo,
-                                                    int32_t* __restrict__ dplus) {
+                                                    int32_t* __restrict__ dplus, int64_t r_base) {
   __shared__ int32_t s[CAP];
   __shared__ int below;
-  const int64_t r = r_lo + blockIdx.x;
-  const int d = dr[r];
-  const int64_t in0 = rp[perm[r]];
+  const int64_t r = r_lo + blockIdx.x, li = r - r_base;
+  const int d = dr[li];
+  const int64_t in0 = rp[perm[li]];
   int P = 1;
   while (P < d) P <<= 1;
   if (threadIdx.x == 0) below = 0;
@@ -188,11 +196,11 @@ __global__ __launch_bounds__(NT) void k_row_bitonic(const int64_t* __restrict__ 
       __syncthreads();
     }
   }
-  int32_t* out = ncol + nptr[r];
+  int32_t* out = ncol + nptr[li];
   for (int i = threadIdx.x; i < d; i += NT) out[i] = s[i];
   if (threadIdx.x == 0) {
-    dlo[r] = below;
-    dplus[r] = d - below;
+    dlo[li] = below;
+    dplus[li] = d - below;
   }
 }
 
@@ -207,14 +215,14 @@ __global__ __launch_bounds__(BM_NT) void k_row_bitmap(const int64_t* __restrict_
                                                       const int32_t* __restrict__ dr, int64_t n,
                                                       int64_t r_lo, int32_t* __restrict__ ncol,
                                                       int32_t* __restrict__ dlo,
-                                                      int32_t* __restrict__ dplus) {
+                                                      int32_t* __restrict__ dplus, int64_t r_base) {
   __shared__ uint32_t bm[BM_WORDS];
   __shared__ int64_t wsum[BM_NT / WAVE];
   __shared__ int below;
-  const int64_t r = r_lo + blockIdx.x;
-  const int d = dr[r];
-  const int64_t in0 = rp[perm[r]];
-  int32_t* out = ncol + nptr[r];
+  const int64_t r = r_lo + blockIdx.x, li = r - r_base;
+  const int d = dr[li];
+  const int64_t in0 = rp[perm[li]];
+  int32_t* out = ncol + nptr[li];
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid / WAVE;
   if (tid == 0) below = 0;
   int64_t written = 0;
@@ -262,8 +270,8 @@ __global__ __launch_bounds__(BM_NT) void k_row_bitmap(const int64_t* __restrict_
   if (mybelow) atomicAdd(&below, mybelow);
   __syncthreads();
   if (tid == 0) {
-    dlo[r] = below;
-    dplus[r] = d - below;
+    dlo[li] = below;
+    dplus[li] = d - below;
   }
 }
 
@@ -293,11 +301,47 @@ inline unsigned blocks_for(int64_t n, int nt) { return (unsigned)ceil_div(n > 0 
 
 // Degree thresholds of the row-sort classes; the same table decides which
 // kernel sorts each rank range.
-static const int kThr[] = {1, 8, 16, 32, 64, 256, 1024, 4096, 32768};
+static const int kThr[] = {1, 8, 16, 32, 64, 256, 1024, 2048, 2048};
 static constexpr int kNThr = sizeof(kThr) / sizeof(kThr[0]);
 
-void build_prep(const int64_t* rp, const int32_t* col, int64_t n, int64_t nnz, bool validate,
-                Prep& P, Classes& C, Scal* scal, Scal* scal_host, Arena& tmp, hipStream_t s) {
+void sort_rows(const int64_t* rp, const int32_t* col, const int32_t* perm, const int32_t* rank,
+               const int64_t* nptr, const int32_t* dr, int64_t n, int64_t r_lo, int64_t r_hi,
+               const int64_t* bnd, int32_t* ncol, int32_t* dlo, int32_t* dplus, int64_t r_base,
+               hipStream_t s) {
+  // class boundaries clipped to [r_lo, r_hi)
+  int64_t b[kNThr];
+  for (int i = 0; i < kNThr; i++) b[i] = std::min(std::max(bnd[i], r_lo), r_hi);
+  auto small = [&](auto tag, int64_t lo, int64_t hi) {
+    constexpr int G = decltype(tag)::value;
+    if (hi <= lo) return;
+    int64_t threads = (hi - lo) * G;
+    k_row_small<G><<<blocks_for(threads, 256), 256, 0, s>>>(rp, col, perm, rank, nptr, dr, lo, hi,
+                                                            ncol, dlo, dplus, r_base);
+  };
+  small(std::integral_constant<int, 1>{}, r_lo, b[0]);
+  small(std::integral_constant<int, 8>{}, b[0], b[1]);
+  small(std::integral_constant<int, 16>{}, b[1], b[2]);
+  small(std::integral_constant<int, 32>{}, b[2], b[3]);
+  small(std::integral_constant<int, 64>{}, b[3], b[4]);
+  if (b[5] > b[4])
+    k_row_bitonic<256, 128><<<(unsigned)(b[5] - b[4]), 128, 0, s>>>(
+        rp, col, perm, rank, nptr, dr, b[4], ncol, dlo, dplus, r_base);
+  if (b[6] > b[5])
+    k_row_bitonic<1024, 256><<<(unsigned)(b[6] - b[5]), 256, 0, s>>>(
+        rp, col, perm, rank, nptr, dr, b[5], ncol, dlo, dplus, r_base);
+  if (b[7] > b[6])
+    k_row_bitonic<2048, 512><<<(unsigned)(b[7] - b[6]), 512, 0, s>>>(
+        rp, col, perm, rank, nptr, dr, b[6], ncol, dlo, dplus, r_base);
+  if (r_hi > b[8])
+    k_row_bitmap<<<(unsigned)(r_hi - b[8]), BM_NT, 0, s>>>(rp, col, perm, rank, nptr, dr, n, b[8],
+                                                           ncol, dlo, dplus, r_base);
+}
+
+int row_class_count() { return kNThr; }
+const int* row_class_thresholds() { return kThr; }
+
+void degree_order(const int64_t* rp, const int32_t* col, int64_t n, int64_t nnz, bool validate,
+                  Prep& P, Classes& C, Scal* scal, Scal* scal_host, Arena& tmp, hipStream_t s) {
   P.n = n;
   P.nnz = nnz;
   P.m = nnz / 2;
@@ -312,7 +356,7 @@ void build_prep(const int64_t* rp, const int32_t* col, int64_t n, int64_t nnz, b
   int32_t* vB = tmp.take<int32_t>(n);
   int64_t* rtmp = tmp.take<int64_t>(radix_tmp_elems(n, 8));
   if (!kA || !kB || !vB || !rtmp) throw Fail(M4_EINTERNAL, "workspace too small (build)");
-  k_degree<<<blocks_for(n, NT), NT, 0, s>>>(rp, n, kA, scal);
+  k_degree<<<blocks_for(n, 1024), 1024, 0, s>>>(rp, n, kA, scal);
   M4_HIP(hipMemcpyAsync(scal_host, scal, sizeof(Scal), hipMemcpyDeviceToHost, s));
   M4_HIP(hipStreamSynchronize(s));
   if (scal_host->err) throw Fail(M4_EINVAL, "CSR is not simple, symmetric and sorted");
@@ -353,35 +397,15 @@ void build_prep(const int64_t* rp, const int32_t* col, int64_t n, int64_t nnz, b
   M4_HIP(hipStreamSynchronize(s));
   C.r1 = b[0];
   for (int i = 0; i < kNThr; i++) C.bound[i] = b[i];
+}
 
+void build_prep(const int64_t* rp, const int32_t* col, int64_t n, int64_t nnz, bool validate,
+                Prep& P, Classes& C, Scal* scal, Scal* scal_host, Arena& tmp, hipStream_t s) {
+  degree_order(rp, col, n, nnz, validate, P, C, scal, scal_host, tmp, s);
   // relabel and sort every row, by degree class
-  auto small = [&](auto tag, int64_t lo, int64_t hi) {
-    constexpr int G = decltype(tag)::value;
-    if (hi <= lo) return;
-    int64_t threads = (hi - lo) * G;
-    k_row_small<G><<<blocks_for(threads, 256), 256, 0, s>>>(rp, col, P.perm, P.rank, P.nptr, P.dr,
-                                                            lo, hi, P.ncol, P.dlo, P.dplus);
-  };
-  small(std::integral_constant<int, 1>{}, 0, b[0]);
-  small(std::integral_constant<int, 8>{}, b[0], b[1]);
-  small(std::integral_constant<int, 16>{}, b[1], b[2]);
-  small(std::integral_constant<int, 32>{}, b[2], b[3]);
-  small(std::integral_constant<int, 64>{}, b[3], b[4]);
-  if (b[5] > b[4])
-    k_row_bitonic<256, 128><<<(unsigned)(b[5] - b[4]), 128, 0, s>>>(
-        rp, col, P.perm, P.rank, P.nptr, P.dr, b[4], P.ncol, P.dlo, P.dplus);
-  if (b[6] > b[5])
-    k_row_bitonic<1024, 256><<<(unsigned)(b[6] - b[5]), 256, 0, s>>>(
-        rp, col, P.perm, P.rank, P.nptr, P.dr, b[5], P.ncol, P.dlo, P.dplus);
-  if (b[7] > b[6])
-    k_row_bitonic<4096, 512><<<(unsigned)(b[7] - b[6]), 512, 0, s>>>(
-        rp, col, P.perm, P.rank, P.nptr, P.dr, b[6], P.ncol, P.dlo, P.dplus);
-  if (b[8] > b[7])
-    k_row_bitonic<32768, 1024><<<(unsigned)(b[8] - b[7]), 1024, 0, s>>>(
-        rp, col, P.perm, P.rank, P.nptr, P.dr, b[7], P.ncol, P.dlo, P.dplus);
-  if (n > b[8])
-    k_row_bitmap<<<(unsigned)(n - b[8]), BM_NT, 0, s>>>(rp, col, P.perm, P.rank, P.nptr, P.dr, n,
-                                                        b[8], P.ncol, P.dlo, P.dplus);
+  sort_rows(rp, col, P.perm, P.rank, P.nptr, P.dr, n, 0, n, C.bound, P.ncol, P.dlo, P.dplus, 0, s);
+  int64_t* stmp = tmp.take<int64_t>(scan_tmp_elems(n));
+  if (!stmp) throw Fail(M4_EINTERNAL, "workspace too small (build)");
   scan_i32(P.dplus, n, P.optr, stmp, s);
 }
 
@@ -400,6 +424,7 @@ size_t build_tmp_bytes(int64_t n, int64_t nnz) {
   add(n * 4);
   add(n * 4);
   add(radix_tmp_elems(n, 8) * 8);
+  add(scan_tmp_elems(n) * 8);
   add(scan_tmp_elems(n) * 8);
   add(64 * 4);
   add(64 * 8);

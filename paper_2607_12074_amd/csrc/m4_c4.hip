@@ -38,15 +38,15 @@ struct C4Args {
   const int32_t* dr;
   const int32_t* dlo;
   const int64_t* wub;
+  const int32_t* row_len;  // stored prefix of every row (null: full rows)
   int64_t r1;
   int bucket;
   int slot;
   unsigned int* work;
   Scal* scal;
   uint32_t flags;
-  int32_t* cur;  // per-block cursor scratch (window bucket)
-  int32_t* end;
-  int64_t seg_cap;
+  const int64_t* seg_off;  // window owners: first descriptor of each owner
+  int4* desc;              // window owners: per-segment cursor descriptors
 };
 
 // wedge bound of every owner: G lanes cooperate on one row, 4 loads in flight
@@ -57,11 +57,16 @@ __global__ __launch_bounds__(256) void k_c4_plan(const int64_t* __restrict__ npt
                                                  const int32_t* __restrict__ dlo, int64_t r_lo,
                                                  int64_t r_hi, int64_t r1, int light_max,
                                                  int64_t* __restrict__ wub,
-                                                 uint32_t* __restrict__ key) {
+                                                 uint32_t* __restrict__ key, int64_t own_lo,
+                                                 int64_t own_hi) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t u = r_lo + t / G;
   int j = (int)(t % G);
   bool ok = u < r_hi;
+  if (ok && (u < own_lo || u >= own_hi)) {
+    if (j == 0) key[u] = CB_NONE;
+    ok = false;
+  }
   int nl = ok ? dlo[u] : 0;
   int64_t b = ok ? nptr[u] : 0;
   int64_t s = 0;
@@ -92,8 +97,13 @@ __global__ __launch_bounds__(1024) void k_c4_plan_big(const int64_t* __restrict_
                                                       const int32_t* __restrict__ dlo, int64_t r_lo,
                                                       int64_t r1, int light_max,
                                                       int64_t* __restrict__ wub,
-                                                      uint32_t* __restrict__ key) {
+                                                      uint32_t* __restrict__ key, int64_t own_lo,
+                                                      int64_t own_hi) {
   int64_t u = r_lo + blockIdx.x;
+  if (u < own_lo || u >= own_hi) {
+    if (threadIdx.x == 0) key[u] = CB_NONE;
+    return;
+  }
   int nl = dlo[u];
   int64_t b = nptr[u];
   int64_t s = 0;
@@ -129,13 +139,19 @@ __global__ __launch_bounds__(H_NT) void k_c4_hash(C4Args A) {
     hkey[i] = -1;
     hcnt[i] = 0;
   }
+  constexpr int GRAB = 8;
+  int64_t item = 0, last = 0;
   for (;;) {
-    if (tid == 0) s_item = (int)atomicAdd(A.work, 1u);
-    __syncthreads();
-    const int64_t item = s_item;
-    __syncthreads();
-    if (item >= cnt) break;
+    if (item == last) {
+      if (tid == 0) s_item = (int)atomicAdd(A.work, (unsigned)GRAB);
+      __syncthreads();
+      item = s_item;
+      __syncthreads();
+      if (item >= cnt) break;
+      last = item + GRAB < cnt ? item + GRAB : cnt;
+    }
     const int32_t u = A.order[b0 + item];
+    item++;
     const int nl = A.dlo[u];
     const int64_t base = A.nptr[u];
     int64_t wb = A.wub[u];
@@ -153,7 +169,7 @@ __global__ __launch_bounds__(H_NT) void k_c4_hash(C4Args A) {
       if (tid < nc) {
         int32_t v = A.ncol[base + c0 + tid];
         sst[tid] = (int32_t)A.nptr[v];
-        len = A.dr[v];
+        len = A.row_len ? A.row_len[v] : A.dr[v];
       }
       int64_t tot;
       int64_t ex = block_excl_scan64<H_NT>(len, &tot);
@@ -198,8 +214,58 @@ __global__ __launch_bounds__(H_NT) void k_c4_hash(C4Args A) {
 }
 
 // -------------------------------------------------------- window bucket
-constexpr int W_NT = 1024, W_GROUP = 16, W_GROUPS = W_NT / W_GROUP;
+// Segment descriptors of the window owners: for lower neighbour v of owner u
+// the cursor into row v (first entry >= r1), the end of the prefix below u,
+// and the value at the cursor.  Built once per owner by a block of its own.
+__global__ __launch_bounds__(256) void k_c4_desc(const int32_t* __restrict__ order,
+                                                 const int64_t* __restrict__ start,
+                                                 const int64_t* __restrict__ seg_off,
+                                                 const int64_t* __restrict__ nptr,
+                                                 const int32_t* __restrict__ dlo,
+                                                 const int32_t* __restrict__ ncol,
+                                                 const int32_t* __restrict__ lowcut,
+                                                 const int32_t* __restrict__ row_len, int64_t r1,
+                                                 int4* __restrict__ desc) {
+  const int64_t h = blockIdx.x;
+  const int32_t u = order[start[CB_WIN16] + h];
+  const int64_t so = seg_off[h], base = nptr[u];
+  const int nl = dlo[u];
+  for (int i = threadIdx.x; i < nl; i += 256) {
+    const int32_t v = ncol[base + i];
+    const int64_t rs = nptr[v];
+    const int64_t rend = row_len ? rs + row_len[v] : nptr[v + 1];
+    const int64_t e = lower_index(ncol, rs + dlo[v], rend, u);  // position of u
+    // first entry >= r1: precomputed for full rows, searched for stored prefixes
+    int64_t c = lowcut ? rs + lowcut[v] : lower_index(ncol, rs, e, (int32_t)r1);
+    if (c > e) c = e;
+    desc[so + i] = make_int4((int)c, (int)e, c < e ? ncol[c] : INT_MAX, 0);
+  }
+}
 
+// entries below r1 (degree <= 1) at the head of every sorted row
+__global__ void k_lowcut(const int64_t* __restrict__ nptr, const int32_t* __restrict__ ncol,
+                         const int32_t* __restrict__ row_len, int64_t n, int64_t r1,
+                         int32_t* __restrict__ lowcut) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int64_t rend = row_len ? nptr[v] + row_len[v] : nptr[v + 1];
+  lowcut[v] = (int32_t)(lower_index(ncol, nptr[v], rend, (int32_t)r1) - nptr[v]);
+}
+
+__global__ void k_c4_heavy_len(const int32_t* __restrict__ order, const int64_t* __restrict__ start,
+                               const int32_t* __restrict__ dlo, int32_t* __restrict__ len) {
+  const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t b = start[CB_WIN16], H = start[CB_WIN32 + 1] - b;
+  if (h < H) len[h] = dlo[order[b + h]];
+}
+
+constexpr int W_NT = 1024, W_GL = 8, W_NG = W_NT / W_GL, W_NCH = 8;
+
+// One heavy owner per workgroup, windows in order.  Each 8-lane group walks
+// its share of the owner's segments; while it counts one segment the loads
+// of the next segment's first 64 entries and the descriptor after that are
+// already in flight.  A segment whose next value lies beyond the window
+// costs only its descriptor.
 template <bool NARROW>
 __global__ __launch_bounds__(W_NT) void k_c4_window(C4Args A) {
   constexpr int WIN = NARROW ? C4_WIN16 : C4_WIN32;
@@ -207,11 +273,12 @@ __global__ __launch_bounds__(W_NT) void k_c4_window(C4Args A) {
   __shared__ uint32_t cnt[WORDS];
   __shared__ int s_item;
   const int tid = threadIdx.x, lane = tid & (WAVE - 1);
-  const int g = tid / W_GROUP, gl = tid & (W_GROUP - 1);
-  const int gshift = lane & ~(W_GROUP - 1);
+  const int g = tid / W_GL, gl = tid & (W_GL - 1);
+  const int gshift = lane & ~(W_GL - 1);
+  const uint64_t gmask = (1ull << W_GL) - 1;
   const int64_t b0 = A.start[A.bucket], cnt_items = A.start[A.bucket + 1] - b0;
-  int32_t* cur = A.cur + (int64_t)blockIdx.x * A.seg_cap;
-  int32_t* end = A.end + (int64_t)blockIdx.x * A.seg_cap;
+  const int64_t hbase = b0 - A.start[CB_WIN16];
+  const int4 kEmpty = make_int4(0, 0, INT_MAX, 0);
   u128_t acc = 0;
   unsigned long long wedges = 0, owners = 0, segs = 0, visits = 0;
   for (;;) {
@@ -221,51 +288,82 @@ __global__ __launch_bounds__(W_NT) void k_c4_window(C4Args A) {
     __syncthreads();
     if (item >= cnt_items) break;
     // heaviest owners (highest ranks) first
-    const int32_t u = A.order[b0 + cnt_items - 1 - item];
-    const int nl = A.dlo[u];
-    const int64_t base = A.nptr[u];
+    const int64_t pos = cnt_items - 1 - item;
+    const int32_t u = A.order[b0 + pos];
+    const int64_t so = A.seg_off[hbase + pos];
+    const int nl = (int)(A.seg_off[hbase + pos + 1] - so);
+    int4* D = A.desc + so;
     if (tid == 0) {
       owners++;
       segs += (unsigned long long)nl;
       visits += (unsigned long long)nl * (unsigned long long)((u - A.r1 + WIN - 1) / WIN);
     }
-    for (int i = tid; i < nl; i += W_NT) {
-      int32_t v = A.ncol[base + i];
-      int64_t rs = A.nptr[v];
-      int64_t e = lower_index(A.ncol, rs + A.dlo[v], A.nptr[v + 1], u);  // position of u
-      int64_t c = lower_index(A.ncol, rs, e, (int32_t)A.r1);
-      cur[i] = (int32_t)c;
-      end[i] = (int32_t)e;
-    }
-    __syncthreads();
     for (int64_t lo = A.r1; lo < u; lo += WIN) {
-      const int64_t hi = lo + WIN < u ? lo + WIN : u;
+      const int32_t hi = (int32_t)(lo + WIN < u ? lo + WIN : u);
       for (int i = tid; i < WORDS; i += W_NT) cnt[i] = 0;
       __syncthreads();
-      for (int sgi = g; sgi < nl; sgi += W_GROUPS) {
-        int32_t c = cur[sgi];
-        const int32_t e = end[sgi];
-        for (;;) {
-          const int32_t idx = c + gl;
-          const int32_t w = idx < e ? A.ncol[idx] : INT_MAX;
-          const bool in = w < hi;
-          if (in) {
-            const uint32_t o = (uint32_t)(w - lo);
-            if (NARROW) {
-              const uint32_t sh = (o & 1u) << 4;
-              const uint32_t old = atomicAdd(&cnt[o >> 1], 1u << sh);
-              acc += (old >> sh) & 0xffffu;
-            } else {
-              acc += atomicAdd(&cnt[o], 1u);
-            }
-            wedges++;
-          }
-          const uint64_t bal = (__ballot(in) >> gshift) & ((1ull << W_GROUP) - 1);
-          const int nin = __popcll(bal);
-          c += nin;
-          if (nin < W_GROUP) break;
+      int sg = g;
+      int4 dA = sg < nl ? D[sg] : kEmpty;
+      int4 dB = sg + W_NG < nl ? D[sg + W_NG] : kEmpty;
+      int32_t wa[W_NCH];
+#pragma unroll
+      for (int k2 = 0; k2 < W_NCH; k2++) {
+        const int32_t idx = dA.x + gl + W_GL * k2;
+        wa[k2] = (dA.z < hi && idx < dA.y) ? A.ncol[idx] : INT_MAX;
+      }
+      while (sg < nl) {
+        const int s2 = sg + 2 * W_NG;
+        const int4 dC = s2 < nl ? D[s2] : kEmpty;
+        int32_t wb[W_NCH];
+#pragma unroll
+        for (int k2 = 0; k2 < W_NCH; k2++) {
+          const int32_t idx = dB.x + gl + W_GL * k2;
+          wb[k2] = (dB.z < hi && idx < dB.y) ? A.ncol[idx] : INT_MAX;
         }
-        if (gl == 0) cur[sgi] = c;
+        if (dA.z < hi) {  // uniform in the group
+          int32_t c = dA.x, vnext = INT_MAX;
+          for (;;) {
+            int tot = 0;
+            bool stop = false;
+#pragma unroll
+            for (int k2 = 0; k2 < W_NCH; k2++) {
+              if (!stop) {
+                const bool in = wa[k2] < hi;
+                if (in) {
+                  const uint32_t o = (uint32_t)(wa[k2] - (int32_t)lo);
+                  if (NARROW) {
+                    const uint32_t sh = (o & 1u) << 4;
+                    const uint32_t old = atomicAdd(&cnt[o >> 1], 1u << sh);
+                    acc += (old >> sh) & 0xffffu;
+                  } else {
+                    acc += atomicAdd(&cnt[o], 1u);
+                  }
+                  wedges++;
+                }
+                // rows are sorted: the entries inside the window are a prefix
+                const int nin = __popcll((__ballot(in) >> gshift) & gmask);
+                tot += nin;
+                if (nin < W_GL) {
+                  vnext = __shfl(wa[k2], gshift + nin, WAVE);
+                  stop = true;
+                }
+              }
+            }
+            c += tot;
+            if (stop) break;
+#pragma unroll
+            for (int k2 = 0; k2 < W_NCH; k2++) {
+              const int32_t idx = c + gl + W_GL * k2;
+              wa[k2] = idx < dA.y ? A.ncol[idx] : INT_MAX;
+            }
+          }
+          if (gl == 0) D[sg] = make_int4(c, dA.y, vnext, 0);
+        }
+        sg += W_NG;
+        dA = dB;
+        dB = dC;
+#pragma unroll
+        for (int k2 = 0; k2 < W_NCH; k2++) wa[k2] = wb[k2];
       }
       __syncthreads();
     }
@@ -285,7 +383,8 @@ inline unsigned blocks_for(int64_t n, int nt) { return (unsigned)ceil_div(n > 0 
 }  // namespace
 
 void c4_run(const Prep& P, const Classes& C, Scal* scal, const Tuning& tu, uint32_t flags,
-            Arena& tmp, hipStream_t s, int num_cu, KTimer* kt) {
+            Arena& tmp, hipStream_t s, int num_cu, KTimer* kt,
+            const std::function<char*(size_t)>& big_scratch) {
   const int64_t n = P.n;
   if (n == 0 || P.m == 0) return;
   int64_t* wub = tmp.take<int64_t>(n);
@@ -293,10 +392,11 @@ void c4_run(const Prep& P, const Classes& C, Scal* scal, const Tuning& tu, uint3
   int32_t* order = tmp.take<int32_t>(n);
   int64_t* rtmp = tmp.take<int64_t>(radix_tmp_elems(n, 2));
   int64_t* start = tmp.take<int64_t>(8);
-  const int64_t seg_cap = C.dmax > 0 ? C.dmax : 1;
-  int32_t* cur = tmp.take<int32_t>((size_t)seg_cap * num_cu);
-  int32_t* end = tmp.take<int32_t>((size_t)seg_cap * num_cu);
-  if (!wub || !key || !order || !rtmp || !start || !cur || !end)
+  int32_t* hlen = tmp.take<int32_t>(n);
+  int64_t* seg_off = tmp.take<int64_t>(n + 1);
+  int64_t* stmp = tmp.take<int64_t>(scan_tmp_elems(n));
+  int32_t* lowcut = tmp.take<int32_t>(n);
+  if (!wub || !key || !order || !rtmp || !start || !hlen || !seg_off || !stmp || !lowcut)
     throw Fail(M4_EINTERNAL, "workspace too small (c4)");
   fill_u32(&scal->work[0], 0, 8, s);
   const int light = tu.c4_light_max;
@@ -306,14 +406,33 @@ void c4_run(const Prep& P, const Classes& C, Scal* scal, const Tuning& tu, uint3
   if (kt) kt->begin(M4_K_C4_PLAN, s);
   if (b64 > 0)
     k_c4_plan<8><<<blocks_for(b64 * 8, 256), 256, 0, s>>>(P.nptr, P.ncol, P.dr, P.dlo, 0, b64,
-                                                          C.r1, light, wub, key);
+                                                          C.r1, light, wub, key, P.own_lo, P.hi());
   if (b4096 > b64)
     k_c4_plan<64><<<blocks_for((b4096 - b64) * 64, 256), 256, 0, s>>>(
-        P.nptr, P.ncol, P.dr, P.dlo, b64, b4096, C.r1, light, wub, key);
+        P.nptr, P.ncol, P.dr, P.dlo, b64, b4096, C.r1, light, wub, key, P.own_lo, P.hi());
   if (n > b4096)
     k_c4_plan_big<<<(unsigned)(n - b4096), 1024, 0, s>>>(P.nptr, P.ncol, P.dr, P.dlo, b4096, C.r1,
-                                                         light, wub, key);
+                                                         light, wub, key, P.own_lo, P.hi());
   radix_pass(key, nullptr, n, 0, 2, nullptr, order, rtmp, start, s);
+  int64_t hstart[CB_N + 1];
+  M4_HIP(hipMemcpyAsync(hstart, start, sizeof(hstart), hipMemcpyDeviceToHost, s));
+  M4_HIP(hipStreamSynchronize(s));
+  const int64_t H = hstart[CB_WIN32 + 1] - hstart[CB_WIN16];
+  int4* desc = nullptr;
+  if (H > 0) {
+    k_c4_heavy_len<<<blocks_for(H, 256), 256, 0, s>>>(order, start, P.dlo, hlen);
+    scan_i32(hlen, H, seg_off, stmp, s);
+    int64_t nseg = 0;
+    M4_HIP(hipMemcpyAsync(&nseg, seg_off + H, 8, hipMemcpyDeviceToHost, s));
+    M4_HIP(hipStreamSynchronize(s));
+    desc = reinterpret_cast<int4*>(big_scratch((size_t)(nseg > 0 ? nseg : 1) * sizeof(int4)));
+    if (!desc) throw Fail(M4_ENOMEM, "no room for 4-cycle segment descriptors");
+    // with stored prefixes only the partition's rows are valid: no full pass
+    if (!P.row_len)
+      k_lowcut<<<blocks_for(n, 256), 256, 0, s>>>(P.nptr, P.ncol, P.row_len, n, C.r1, lowcut);
+    k_c4_desc<<<(unsigned)H, 256, 0, s>>>(order, start, seg_off, P.nptr, P.dlo, P.ncol,
+                                          P.row_len ? nullptr : lowcut, P.row_len, C.r1, desc);
+  }
   if (kt) kt->end(M4_K_C4_PLAN, s);
 
   C4Args A{};
@@ -324,31 +443,37 @@ void c4_run(const Prep& P, const Classes& C, Scal* scal, const Tuning& tu, uint3
   A.dr = P.dr;
   A.dlo = P.dlo;
   A.wub = wub;
+  A.row_len = P.row_len;
   A.r1 = C.r1;
   A.scal = scal;
   A.flags = flags;
-  A.cur = cur;
-  A.end = end;
-  A.seg_cap = seg_cap;
+  A.seg_off = seg_off;
+  A.desc = desc;
   // heavy owners first: one 1024-thread workgroup per CU
-  A.bucket = CB_WIN16;
-  A.slot = M4_K_C4_WIN16;
-  A.work = &scal->work[CB_WIN16];
-  if (kt) kt->begin(M4_K_C4_WIN16, s);
-  k_c4_window<true><<<(unsigned)num_cu, W_NT, 0, s>>>(A);
-  if (kt) kt->end(M4_K_C4_WIN16, s);
-  A.bucket = CB_WIN32;
-  A.slot = M4_K_C4_WIN32;
-  A.work = &scal->work[CB_WIN32];
-  if (kt) kt->begin(M4_K_C4_WIN32, s);
-  k_c4_window<false><<<(unsigned)num_cu, W_NT, 0, s>>>(A);
-  if (kt) kt->end(M4_K_C4_WIN32, s);
-  A.bucket = CB_HASH;
-  A.slot = M4_K_C4_HASH;
-  A.work = &scal->work[CB_HASH];
-  if (kt) kt->begin(M4_K_C4_HASH, s);
-  k_c4_hash<<<(unsigned)(num_cu * 4), H_NT, 0, s>>>(A);
-  if (kt) kt->end(M4_K_C4_HASH, s);
+  if (hstart[CB_WIN16 + 1] > hstart[CB_WIN16]) {
+    A.bucket = CB_WIN16;
+    A.slot = M4_K_C4_WIN16;
+    A.work = &scal->work[CB_WIN16];
+    if (kt) kt->begin(M4_K_C4_WIN16, s);
+    k_c4_window<true><<<(unsigned)num_cu, W_NT, 0, s>>>(A);
+    if (kt) kt->end(M4_K_C4_WIN16, s);
+  }
+  if (hstart[CB_WIN32 + 1] > hstart[CB_WIN32]) {
+    A.bucket = CB_WIN32;
+    A.slot = M4_K_C4_WIN32;
+    A.work = &scal->work[CB_WIN32];
+    if (kt) kt->begin(M4_K_C4_WIN32, s);
+    k_c4_window<false><<<(unsigned)num_cu, W_NT, 0, s>>>(A);
+    if (kt) kt->end(M4_K_C4_WIN32, s);
+  }
+  if (hstart[CB_HASH + 1] > hstart[CB_HASH]) {
+    A.bucket = CB_HASH;
+    A.slot = M4_K_C4_HASH;
+    A.work = &scal->work[CB_HASH];
+    if (kt) kt->begin(M4_K_C4_HASH, s);
+    k_c4_hash<<<(unsigned)(num_cu * 4), H_NT, 0, s>>>(A);
+    if (kt) kt->end(M4_K_C4_HASH, s);
+  }
 }
 
 }  // namespace m4

@@ -29,10 +29,10 @@ __global__ __launch_bounds__(CL_NT) void k_closure(const int64_t* __restrict__ n
                                                    const int64_t* __restrict__ optr,
                                                    const int32_t* __restrict__ ncol,
                                                    const int32_t* __restrict__ dr,
-                                                   const uint32_t* __restrict__ t, int64_t n,
-                                                   Scal* scal) {
+                                                   const uint32_t* __restrict__ t, int64_t lo,
+                                                   int64_t hi, Scal* scal) {
   u128_t S = 0, P = 0, D = 0, Paw2 = 0, St = 0;
-  for (int64_t u = (int64_t)blockIdx.x * CL_NT + threadIdx.x; u < n;
+  for (int64_t u = lo + (int64_t)blockIdx.x * CL_NT + threadIdx.x; u < hi;
        u += (int64_t)gridDim.x * CL_NT) {
     const uint64_t du = (uint32_t)dr[u];
     if (du >= 3) S += (u128_t)du * (du - 1) * (du - 2) / 6;
@@ -57,47 +57,23 @@ __global__ __launch_bounds__(CL_NT) void k_closure(const int64_t* __restrict__ n
 // status: 0 ok, 3 a count >= 2^64, 7 internal check failed
 __global__ void k_finalize(Scal* scal) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const u128_t K4 = load_u128(&scal->acc[ACC_K4]);
-  const u128_t C4 = load_u128(&scal->acc[ACC_C4]);
-  const u128_t S = load_u128(&scal->acc[ACC_S]);
-  const u128_t P = load_u128(&scal->acc[ACC_P]);
-  const u128_t D = load_u128(&scal->acc[ACC_D]);
-  const u128_t Paw2 = load_u128(&scal->acc[ACC_PAW2]);
-  const u128_t St = load_u128(&scal->acc[ACC_SUMT]);
-  int status = 0;
-  if (St % 3 != 0 || Paw2 % 2 != 0) status = 7;
-  const u128_t T = St / 3, PawN = Paw2 / 2;
-  u128_t clique = K4, diamond = 0, cycle = 0, paw = 0, star = 0, path = 0;
-  // each subtraction below removes copies inside denser patterns
-  if (D >= 6 * clique) diamond = D - 6 * clique; else status = 7;
-  if (C4 >= diamond + 3 * clique) cycle = C4 - diamond - 3 * clique; else status = 7;
-  if (PawN >= 4 * diamond + 12 * clique) paw = PawN - 4 * diamond - 12 * clique; else status = 7;
-  if (S >= paw + 2 * diamond + 4 * clique) star = S - paw - 2 * diamond - 4 * clique; else status = 7;
-  const u128_t pathN = P - 3 * T;
-  const u128_t sub = 2 * paw + 4 * cycle + 6 * diamond + 12 * clique;
-  if (P >= 3 * T && pathN >= sub) path = pathN - sub; else status = 7;
-  const u128_t res[6] = {star, path, paw, cycle, diamond, clique};
-  const u128_t basis[8] = {T, K4, C4, S, pathN, PawN, D, St};
-  for (int i = 0; i < 8; i++) {
-    if (basis[i] >> 64) { if (!status) status = 3; scal->basis[i] = ~0ull; }
-    else scal->basis[i] = (unsigned long long)basis[i];
-  }
-  for (int i = 0; i < 6; i++) {
-    if (res[i] >> 64) { if (!status) status = 3; scal->out[i] = ~0ull; }
-    else scal->out[i] = (unsigned long long)res[i];
-  }
-  scal->status = status;
+  const u128_t in[7] = {load_u128(&scal->acc[ACC_K4]), load_u128(&scal->acc[ACC_C4]),
+                        load_u128(&scal->acc[ACC_S]),  load_u128(&scal->acc[ACC_P]),
+                        load_u128(&scal->acc[ACC_D]),  load_u128(&scal->acc[ACC_PAW2]),
+                        load_u128(&scal->acc[ACC_SUMT])};
+  scal->status = finalize_basis(in, scal->out, scal->basis);
 }
 
 }  // namespace
 
 void closure_run(const Prep& P, Scal* scal, uint32_t flags, hipStream_t s) {
   (void)flags;
-  if (P.n == 0) return;
-  int64_t blocks = ceil_div(P.n, CL_NT);
+  const int64_t lo = P.own_lo, hi = P.hi();
+  if (hi <= lo) return;
+  int64_t blocks = ceil_div(hi - lo, CL_NT);
   if (blocks > 4096) blocks = 4096;
   k_closure<<<(unsigned)blocks, CL_NT, 0, s>>>(P.nptr, P.dlo, P.dplus, P.optr, P.ncol, P.dr, P.t,
-                                               P.n, scal);
+                                               lo, hi, scal);
 }
 
 void finalize_run(Scal* scal, hipStream_t s) { k_finalize<<<1, 64, 0, s>>>(scal); }

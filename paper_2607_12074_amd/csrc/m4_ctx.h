@@ -33,6 +33,18 @@ bool needs_partition(m4_ctx* c, const m4_csr* g, const m4_opts* o);
 int count_partitioned(m4_ctx* c, const m4_csr* g, const m4_opts* o, uint64_t out[6],
                       m4_stats* st);
 void destroy_ctx_extras(m4_ctx* c);
+// m4_batch.hip -- one persistent fused launch over a packed arena
+struct BatchArgs;
+struct BatchBuffers {
+  DevBuf dev, gscratch;
+  unsigned long long* h_out = nullptr;  // pinned [G][6]
+  int* h_status = nullptr;              // pinned [G]
+  char* h_stage = nullptr;              // pinned copy of a host arena
+  size_t h_out_cap = 0, h_stage_cap = 0;
+  void release();
+};
+struct BatchPlan;
+void destroy_batch_state(m4_ctx* c);
 
 }  // namespace m4
 

@@ -97,4 +97,36 @@ __device__ __forceinline__ int64_t lower_index(const T* a, int64_t lo, int64_t h
   return lo;
 }
 
+// Induced counts from the non-induced basis (Section III-F closure): the
+// inverse of the unit upper-triangular "spanning copies" system, densest
+// pattern first.  in[] = {K4, C4_ni, S, P, D_ni, Paw2, sum_t} as 128-bit sums.
+// Returns 0, 3 (a value >= 2^64) or 7 (a consistency check failed).
+__device__ __forceinline__ int finalize_basis(const u128_t in[7], unsigned long long out[6],
+                                              unsigned long long basis[8]) {
+  const u128_t K4 = in[0], C4 = in[1], S = in[2], P = in[3], D = in[4], Paw2 = in[5],
+               St = in[6];
+  int status = 0;
+  if (St % 3 != 0 || Paw2 % 2 != 0) status = 7;
+  const u128_t T = St / 3, PawN = Paw2 / 2;
+  u128_t clique = K4, diamond = 0, cycle = 0, paw = 0, star = 0, path = 0;
+  if (D >= 6 * clique) diamond = D - 6 * clique; else status = 7;
+  if (C4 >= diamond + 3 * clique) cycle = C4 - diamond - 3 * clique; else status = 7;
+  if (PawN >= 4 * diamond + 12 * clique) paw = PawN - 4 * diamond - 12 * clique; else status = 7;
+  if (S >= paw + 2 * diamond + 4 * clique) star = S - paw - 2 * diamond - 4 * clique; else status = 7;
+  const u128_t pathN = P >= 3 * T ? P - 3 * T : 0;
+  const u128_t sub = 2 * paw + 4 * cycle + 6 * diamond + 12 * clique;
+  if (P >= 3 * T && pathN >= sub) path = pathN - sub; else status = 7;
+  const u128_t res[6] = {star, path, paw, cycle, diamond, clique};
+  const u128_t b[8] = {T, K4, C4, S, pathN, PawN, D, St};
+  for (int i = 0; i < 8; i++) {
+    if (b[i] >> 64) { if (!status) status = 3; if (basis) basis[i] = ~0ull; }
+    else if (basis) basis[i] = (unsigned long long)b[i];
+  }
+  for (int i = 0; i < 6; i++) {
+    if (res[i] >> 64) { if (!status) status = 3; out[i] = ~0ull; }
+    else out[i] = (unsigned long long)res[i];
+  }
+  return status;
+}
+
 }  // namespace m4

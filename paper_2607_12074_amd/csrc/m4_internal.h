@@ -63,6 +63,11 @@ struct Prep {
   int64_t* optr = nullptr;  // oriented edge offsets [n+1]
   int32_t* ncol = nullptr;  // rows in rank space, sorted [nnz]
   uint32_t* t = nullptr;    // triangles per oriented edge [m]
+  // Partitioned runs: only owners in [own_lo, own_hi) are processed and rows
+  // may be stored as a prefix of row_len[v] entries (null: full rows).
+  int64_t own_lo = 0, own_hi = -1;
+  const int32_t* row_len = nullptr;
+  int64_t hi() const { return own_hi < 0 ? n : own_hi; }
 };
 
 // Rank boundaries of degree classes, read back once per graph.
@@ -91,6 +96,8 @@ struct Tuning {
   int tri_wave_max = 64;    // <= WAVE
   int c4_light_max = 2048;  // wedge bound for the hash bucket
   int grid_mult = 8;        // persistent blocks per CU for light kernels
+  int batch_variant = 0;    // batched kernel: 0 = 1024 threads / 96 KiB, 1 = 512 / 40 KiB
+  int batch_light = 128;    // batched kernel: wedge bound of the wavefront hash
 };
 
 // Optional per-launch HIP event pairs (M4_TIMING).
@@ -160,8 +167,21 @@ void fill_u32(void* p, uint32_t v, size_t count32, hipStream_t s);
 size_t build_tmp_bytes(int64_t n, int64_t nnz);
 void build_prep(const int64_t* rp, const int32_t* col, int64_t n, int64_t nnz, bool validate,
                 Prep& P, Classes& C, Scal* scal, Scal* scal_host, Arena& tmp, hipStream_t s);
+// First half of build_prep: degrees, degree order (perm, dr, rank), row
+// offsets nptr and the rank boundaries of the degree classes.
+void degree_order(const int64_t* rp, const int32_t* col, int64_t n, int64_t nnz, bool validate,
+                  Prep& P, Classes& C, Scal* scal, Scal* scal_host, Arena& tmp, hipStream_t s);
 void edge_t_to_input(const Prep& P, const int64_t* rp, const int32_t* col, uint32_t* t_out,
                      hipStream_t s);
+// Relabels rows [r_lo, r_hi) (ranks) through rank[] and sorts them; per-row
+// arrays (perm, nptr, dr, dlo, dplus) are indexed by rank - r_base; bnd are
+// the rank boundaries of the degree classes (row_class_thresholds()).
+void sort_rows(const int64_t* rp, const int32_t* col, const int32_t* perm, const int32_t* rank,
+               const int64_t* nptr, const int32_t* dr, int64_t n, int64_t r_lo, int64_t r_hi,
+               const int64_t* bnd, int32_t* ncol, int32_t* dlo, int32_t* dplus, int64_t r_base,
+               hipStream_t s);
+int row_class_count();
+const int* row_class_thresholds();
 
 // m4_tri.hip
 size_t tri_tmp_bytes(int64_t n, int64_t nnz, int dplus_max_bound);
@@ -173,7 +193,8 @@ void tri_run(const Prep& P, Scal* scal, const Tuning& tu, uint32_t flags, uint32
 
 // m4_c4.hip
 void c4_run(const Prep& P, const Classes& C, Scal* scal, const Tuning& tu, uint32_t flags,
-            Arena& tmp, hipStream_t s, int num_cu, KTimer* kt);
+            Arena& tmp, hipStream_t s, int num_cu, KTimer* kt,
+            const std::function<char*(size_t)>& big_scratch);
 
 // m4_closure.hip
 void closure_run(const Prep& P, Scal* scal, uint32_t flags, hipStream_t s);

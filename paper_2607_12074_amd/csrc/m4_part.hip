@@ -1,45 +1,507 @@
-// m4_part.hip -- halo-partitioned path (graphs larger than a device budget).
+// m4_part.hip -- halo-partitioned path for graphs larger than a device budget
+// (ownership-preserving partitioned derivation, Section III-E).
+//
+// The graph stays in host memory.  Its degree order is computed on the device
+// (n-sized arrays only), then the relabelled, sorted rank-space CSR is built
+// by streaming chunks of rows through the row-sort kernels into pinned host
+// memory.  The anchors are then counted over contiguous rank ranges of
+// owners, each range uploaded with its halo (the rows its anchors read):
+//   triangles / 4-cliques: owner = lowest vertex; the range's out-lists plus
+//     the out-lists of their out-neighbours (radius-1 oriented halo);
+//   4-cycles: owner = highest vertex; the lower lists of the range plus the
+//     rows of their lower neighbours, cut below the range's upper end;
+//   closure: owner = lower end of every oriented edge; out-lists only.
+// Every anchor is counted by exactly the one range holding its owner, linear
+// sums add across ranges, and the per-edge triangle counts live in one device
+// array that every range adds into, so the closure sees complete t_e (the
+// sum of C(t_e, 2) is not linear in the ranges).  Integer adds commute, so
+// the result equals the resident count bit for bit.
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <vector>
+
 #include "m4_ctx.h"
+#include "m4_device.h"
 
 namespace m4 {
 
-bool needs_partition(m4_ctx* c, const m4_csr* g, const m4_opts* o) {
-  (void)c;
-  (void)g;
-  if (!o) return false;
-  return (o->flags & M4_FORCE_PARTITION) || o->device_budget_bytes > 0;
+namespace {
+
+static size_t al(size_t b) { return (b + 255) & ~size_t(255); }
+
+// nptr_p[v] = val for every (v, val) of a partition's row table
+__global__ void k_scatter_rows(const int64_t* __restrict__ pairs, int64_t cnt,
+                               int64_t* __restrict__ nptr_p, int32_t* __restrict__ row_len,
+                               const int32_t* __restrict__ lens) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cnt) return;
+  const int64_t v = pairs[2 * i], off = pairs[2 * i + 1];
+  nptr_p[v] = off;
+  if (row_len) row_len[v] = lens[i];
 }
+
+struct Pinned {
+  char* p = nullptr;
+  size_t cap = 0;
+  void ensure(size_t b) {
+    if (b <= cap) return;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    cap = 0;
+    M4_HIP(hipHostMalloc((void**)&p, b, hipHostMallocDefault));
+    cap = b;
+  }
+  ~Pinned() {
+    if (p) (void)hipHostFree(p);
+  }
+};
+
+// rank-space CSR in host memory
+struct HostCsr {
+  int64_t n = 0, nnz = 0, m = 0;
+  std::vector<int32_t> perm, rank, dr, dlo, dplus;
+  std::vector<int64_t> nptr, optr;
+  Pinned ncol;  // int32[nnz]
+  const int32_t* col() const { return reinterpret_cast<const int32_t*>(ncol.p); }
+};
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+}  // namespace
+
+struct PartState {
+  HostCsr H;
+  Pinned stage[2];
+  std::vector<int64_t> pairs;
+  std::vector<int32_t> lens;
+};
+
+size_t resident_bytes(int64_t n, int64_t nnz, int num_cu) {
+  return prep_bytes(n, nnz) + stage_tmp_bytes(n, nnz, 1, num_cu) + (size_t)(n + 1) * 8 +
+         (size_t)nnz * 4 + (size_t)nnz * 8;
+}
+
+bool needs_partition(m4_ctx* c, const m4_csr* g, const m4_opts* o) {
+  if (!o) return false;
+  if (o->flags & M4_FORCE_PARTITION) return true;
+  return o->device_budget_bytes > 0 &&
+         resident_bytes(g->n, g->nnz, c->num_cu) > o->device_budget_bytes;
+}
+
+void destroy_ctx_extras(m4_ctx* c) {
+  destroy_batch_state(c);
+  delete c->part;
+  c->part = nullptr;
+}
+
+namespace {
+
+// Device arena carved from c->extra, never larger than the budget.
+struct Dev {
+  char* base;
+  size_t cap, used = 0;
+  template <typename T>
+  T* take(size_t count) {
+    size_t b = al(count * sizeof(T) + 8);
+    if (used + b > cap) throw Fail(M4_ENOMEM, "device budget too small for this partition");
+    T* p = reinterpret_cast<T*>(base + used);
+    used += b;
+    return p;
+  }
+};
+
+}  // namespace
 
 int count_partitioned(m4_ctx* c, const m4_csr* g, const m4_opts* o, uint64_t out[6],
                       m4_stats* st) {
-  (void)g;
-  (void)o;
-  (void)out;
-  (void)st;
-  return set_error(c, M4_EINVAL, "partitioned path not available");
-}
+  hipStream_t s = (o && o->hip_stream) ? (hipStream_t)o->hip_stream : c->stream;
+  const uint32_t flags = o ? o->flags : 0;
+  const Tuning tu = tuning_for(c, o);
+  const int64_t n = g->n, nnz = g->nnz, m = nnz / 2;
+  uint64_t budget = o ? o->device_budget_bytes : 0;
+  if (budget == 0) budget = resident_bytes(n, nnz, c->num_cu) / 3 + (1 << 20);
+  const double t_start = now_ms();
+  double t_h2d = 0;
+  uint64_t h2d_bytes = 0, halo_rows = 0, parts = 0;
 
-void destroy_ctx_extras(m4_ctx* c) { (void)c; }
+  if (!c->part) c->part = new PartState();
+  PartState& PS = *c->part;
+  HostCsr& H = PS.H;
+  H.n = n;
+  H.nnz = nnz;
+  H.m = m;
+
+  // host copy of the input when it lives on the device
+  std::vector<int64_t> hrp;
+  std::vector<int32_t> hcol;
+  const int64_t* rp = g->row_ptr;
+  const int32_t* col = g->col;
+  if (g->on_device) {
+    hrp.resize(n + 1);
+    hcol.resize(nnz);
+    M4_HIP(hipMemcpyAsync(hrp.data(), g->row_ptr, (n + 1) * 8, hipMemcpyDeviceToHost, s));
+    M4_HIP(hipMemcpyAsync(hcol.data(), g->col, nnz * 4, hipMemcpyDeviceToHost, s));
+    M4_HIP(hipStreamSynchronize(s));
+    rp = hrp.data();
+    col = hcol.data();
+  }
+  if (rp[n] != nnz) return set_error(c, M4_ERANGE, "row_ptr[n] != nnz");
+
+  // the device side of the whole call lives in c->extra, sized to the budget
+  c->extra.ensure(budget, s);
+  Dev D{c->extra.ptr, budget};
+  auto up = [&](void* dst, const void* src, size_t bytes) {
+    if (!bytes) return;
+    const double t0 = now_ms();
+    M4_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
+    M4_HIP(hipStreamSynchronize(s));
+    t_h2d += now_ms() - t0;
+    h2d_bytes += bytes;
+  };
+  auto down = [&](void* dst, const void* src, size_t bytes) {
+    if (!bytes) return;
+    M4_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));
+    M4_HIP(hipStreamSynchronize(s));
+  };
+
+  fill_u32(c->scal, 0, sizeof(Scal) / 4, s);
+
+  // ---- 1. degree order on the device (n-sized arrays)
+  Classes C{};
+  {
+    D.used = 0;
+    int64_t* drp = D.take<int64_t>(n + 1);
+    Prep P0;
+    P0.perm = D.take<int32_t>(n + 1);
+    P0.rank = D.take<int32_t>(n + 1);
+    P0.dr = D.take<int32_t>(n + 1);
+    P0.nptr = D.take<int64_t>(n + 1);
+    Arena a;
+    a.base = c->extra.ptr + D.used;
+    a.cap = D.cap - D.used;
+    if (a.cap < build_tmp_bytes(n, nnz)) throw Fail(M4_ENOMEM, "device budget below the degree sort");
+    up(drp, rp, (n + 1) * 8);
+    degree_order(drp, nullptr, n, nnz, false, P0, C, c->scal, c->scal_host, a, s);
+    H.perm.resize(n);
+    H.rank.resize(n);
+    H.dr.resize(n);
+    H.nptr.resize(n + 1);
+    down(H.perm.data(), P0.perm, n * 4);
+    down(H.rank.data(), P0.rank, n * 4);
+    down(H.dr.data(), P0.dr, n * 4);
+    down(H.nptr.data(), P0.nptr, (n + 1) * 8);
+  }
+  H.dlo.assign(n, 0);
+  H.dplus.assign(n, 0);
+  H.ncol.ensure((size_t)nnz * 4 + 4);
+
+  // ---- 2. rank-space rows, streamed in chunks through the row-sort kernels
+  {
+    D.used = 0;
+    int32_t* drank = D.take<int32_t>(n + 1);
+    up(drank, H.rank.data(), n * 4);
+    const size_t fixed = D.used + 64 * 1024;
+    // per row 8 (rp) + 4 (perm) + 8 (nptr) + 12 (dr, dlo, dplus), per entry 8
+    const size_t avail = D.cap > fixed ? D.cap - fixed : 0;
+    int64_t dmax = C.dmax;
+    if ((size_t)dmax * 8 + 64 * 64 > avail) throw Fail(M4_ENOMEM, "device budget below one row");
+    const size_t base_used = D.used;
+    int64_t r0 = 0;
+    while (r0 < n) {
+      // rows [r0, r1): entries * 8 + rows * 40 within the free budget
+      int64_t r1 = r0, ent = 0;
+      while (r1 < n) {
+        const int64_t d = H.dr[r1];
+        if ((size_t)(ent + d) * 8 + (size_t)(r1 - r0 + 1) * 48 + 8 * 256 > avail) break;
+        ent += d;
+        r1++;
+      }
+      if (r1 == r0) throw Fail(M4_ENOMEM, "device budget below one row");
+      const int64_t R = r1 - r0;
+      D.used = base_used;
+      int64_t* crp = D.take<int64_t>(R + 1);
+      int32_t* cperm = D.take<int32_t>(R);
+      int64_t* cnptr = D.take<int64_t>(R + 1);
+      int32_t* cdr = D.take<int32_t>(R);
+      int32_t* cdlo = D.take<int32_t>(R);
+      int32_t* cdplus = D.take<int32_t>(R);
+      int32_t* ccol = D.take<int32_t>(ent + 1);
+      int32_t* cout = D.take<int32_t>(ent + 1);
+      // host staging: input rows of perm[r0..r1) in rank order
+      Pinned& S = PS.stage[0];
+      const size_t sb = al((R + 1) * 8) + al(R * 4) + al((R + 1) * 8) + al(R * 4) + al(ent * 4 + 4);
+      S.ensure(sb);
+      int64_t* hrp2 = reinterpret_cast<int64_t*>(S.p);
+      int32_t* hperm = reinterpret_cast<int32_t*>(S.p + al((R + 1) * 8));
+      int64_t* hnptr = reinterpret_cast<int64_t*>(S.p + al((R + 1) * 8) + al(R * 4));
+      int32_t* hdr = reinterpret_cast<int32_t*>(S.p + 2 * al((R + 1) * 8) + al(R * 4));
+      int32_t* hcc = reinterpret_cast<int32_t*>(S.p + 2 * al((R + 1) * 8) + 2 * al(R * 4));
+      hrp2[0] = 0;
+      for (int64_t i = 0; i < R; i++) {
+        const int32_t v = H.perm[r0 + i];
+        const int64_t d = rp[v + 1] - rp[v];
+        memcpy(hcc + hrp2[i], col + rp[v], d * 4);
+        hrp2[i + 1] = hrp2[i] + d;
+        hperm[i] = (int32_t)i;
+        hnptr[i] = hrp2[i];
+        hdr[i] = (int32_t)d;
+      }
+      hnptr[R] = hrp2[R];
+      up(crp, hrp2, (R + 1) * 8);
+      up(cperm, hperm, R * 4);
+      up(cnptr, hnptr, (R + 1) * 8);
+      up(cdr, hdr, R * 4);
+      up(ccol, hcc, ent * 4);
+      sort_rows(crp, ccol, cperm, drank, cnptr, cdr, n, r0, r1, C.bound, cout, cdlo, cdplus, r0, s);
+      down(H.ncol.p + H.nptr[r0] * 4, cout, ent * 4);
+      down(H.dlo.data() + r0, cdlo, R * 4);
+      down(H.dplus.data() + r0, cdplus, R * 4);
+      r0 = r1;
+    }
+  }
+  H.optr.assign(n + 1, 0);
+  {
+    // oriented offsets: device scan of the out-degrees
+    D.used = 0;
+    int32_t* ddp = D.take<int32_t>(n + 1);
+    int64_t* dop = D.take<int64_t>(n + 2);
+    int64_t* stmp = D.take<int64_t>(scan_tmp_elems(n));
+    up(ddp, H.dplus.data(), n * 4);
+    scan_i32(ddp, n, dop, stmp, s);
+    down(H.optr.data(), dop, (n + 1) * 8);
+  }
+
+  // ---- fixed device arrays of the anchor phases
+  D.used = 0;
+  Prep P;
+  P.n = n;
+  P.nnz = nnz;
+  P.m = m;
+  P.nptr = D.take<int64_t>(n + 1);  // per-partition offsets into the row buffer
+  P.optr = D.take<int64_t>(n + 1);
+  P.dlo = D.take<int32_t>(n + 1);
+  P.dplus = D.take<int32_t>(n + 1);
+  P.dr = D.take<int32_t>(n + 1);
+  P.t = D.take<uint32_t>(m + 1);
+  int32_t* rowlen = D.take<int32_t>(n + 1);
+  up(P.optr, H.optr.data(), (n + 1) * 8);
+  up(P.dlo, H.dlo.data(), n * 4);
+  up(P.dplus, H.dplus.data(), n * 4);
+  up(P.dr, H.dr.data(), n * 4);
+  fill_u32(P.t, 0, (size_t)m, s);
+  const size_t fixed_used = D.used;
+  const size_t tri_tmp = 2 * al(n * 4 + 4) + al(radix_tmp_elems(n, 4) * 8) + 4096;
+  const size_t c4_tmp = 2 * al((n + 1) * 8 + 8) + 4 * al(n * 4 + 4) +
+                        al(radix_tmp_elems(n, 2) * 8) + al(scan_tmp_elems(n) * 8) + 4096;
+  // scratch that a kernel stage sizes at run time comes from the tail of the
+  // budget region, after the stage's work arrays
+  size_t scratch_floor = 0;
+  auto big = [&D, &scratch_floor](size_t bytes) -> char* {
+    const size_t b = al(bytes);
+    if (scratch_floor + b > D.cap) return nullptr;
+    return D.base + (D.cap - b);
+  };
+  std::vector<uint32_t> mark(n, 0);
+  uint32_t stamp = 0;
+  const int32_t* hc = H.col();
+
+  // Uploads rows of a partition: (row, first stored entry, count) triples.
+  struct RowPart {
+    int32_t v;
+    int64_t first;
+    int32_t len;
+  };
+  std::vector<RowPart> rows;
+  auto upload_rows = [&](bool with_len, int64_t nptr_bias_dlo) -> int32_t* {
+    (void)nptr_bias_dlo;
+    int64_t ent = 0;
+    for (const RowPart& r : rows) ent += r.len;
+    D.used = fixed_used;
+    int64_t* dpairs = D.take<int64_t>(2 * rows.size() + 2);
+    int32_t* dlens = D.take<int32_t>(rows.size() + 1);
+    int32_t* dcol = D.take<int32_t>(ent + 1);
+    Pinned& S = PS.stage[parts & 1];
+    const size_t sb = al((2 * rows.size() + 2) * 8) + al((rows.size() + 1) * 4) + al(ent * 4 + 4);
+    S.ensure(sb);
+    int64_t* hp = reinterpret_cast<int64_t*>(S.p);
+    int32_t* hl = reinterpret_cast<int32_t*>(S.p + al((2 * rows.size() + 2) * 8));
+    int32_t* hcc = reinterpret_cast<int32_t*>(S.p + al((2 * rows.size() + 2) * 8) +
+                                              al((rows.size() + 1) * 4));
+    int64_t off = 0;
+    for (size_t i = 0; i < rows.size(); i++) {
+      const RowPart& r = rows[i];
+      memcpy(hcc + off, hc + H.nptr[r.v] + r.first, (size_t)r.len * 4);
+      hp[2 * i] = r.v;
+      hp[2 * i + 1] = off - r.first;  // so that nptr[v] + index-in-row addresses the buffer
+      hl[i] = r.first + r.len;        // stored prefix length (when the row starts at 0)
+      off += r.len;
+    }
+    up(dpairs, hp, rows.size() * 16);
+    up(dlens, hl, rows.size() * 4);
+    up(dcol, hcc, (size_t)ent * 4);
+    k_scatter_rows<<<(unsigned)ceil_div((int64_t)rows.size() + 1, 256), 256, 0, s>>>(
+        dpairs, (int64_t)rows.size(), P.nptr, with_len ? rowlen : nullptr, dlens);
+    halo_rows += rows.size();
+    parts++;
+    return dcol;
+  };
+  auto tmp_arena = [&](size_t need) {
+    Arena a;
+    a.base = c->extra.ptr + D.used;
+    a.cap = need;
+    if (D.used + need > D.cap)
+      throw Fail(M4_ENOMEM, "device budget too small for a partition's work arrays");
+    scratch_floor = D.used + need;
+    return a;
+  };
+
+  // ---- 3. triangle / 4-clique anchors over owner ranges with oriented halos
+  {
+    const size_t cap_rows = D.cap > fixed_used + tri_tmp ? D.cap - fixed_used - tri_tmp : 0;
+    int64_t lo = 0;
+    while (lo < n) {
+      stamp++;
+      rows.clear();
+      size_t bytes = 0;
+      int64_t hi = lo;
+      auto need_row = [&](int32_t v) {
+        if (mark[v] == stamp) return (size_t)0;
+        return (size_t)H.dplus[v] * 4 + 28;
+      };
+      while (hi < n) {
+        // owner hi with its out-list and the out-lists of its out-neighbours
+        size_t add = need_row((int32_t)hi);
+        const int64_t b0 = H.nptr[hi] + H.dlo[hi];
+        for (int64_t j = 0; j < H.dplus[hi]; j++) add += need_row(hc[b0 + j]);
+        if (bytes + add > cap_rows && hi > lo) break;
+        bytes += add;
+        auto put = [&](int32_t v) {
+          if (mark[v] == stamp) return;
+          mark[v] = stamp;
+          rows.push_back({v, (int64_t)H.dlo[v], H.dplus[v]});
+        };
+        put((int32_t)hi);
+        for (int64_t j = 0; j < H.dplus[hi]; j++) put(hc[b0 + j]);
+        hi++;
+      }
+      if (bytes > cap_rows) throw Fail(M4_ENOMEM, "device budget below one owner's halo");
+      P.ncol = upload_rows(false, 1);
+      P.own_lo = lo;
+      P.own_hi = hi;
+      Arena a = tmp_arena(tri_tmp);
+      tri_run(P, c->scal, tu, flags, o ? o->cache_rows : 0, a, s, c->num_cu, big, nullptr);
+      M4_HIP(hipStreamSynchronize(s));
+      lo = hi;
+    }
+  }
+
+  // ---- 4. 4-cycle anchor over owner ranges with lower halos cut below hi
+  {
+    const size_t cap_rows = D.cap > fixed_used + c4_tmp ? D.cap - fixed_used - c4_tmp : 0;
+    std::vector<int32_t> stored(n, 0);
+    int64_t lo = C.r1;
+    // owners below r1 have degree <= 1 and no 4-cycle
+    while (lo < n) {
+      stamp++;
+      rows.clear();
+      std::vector<int32_t> members;
+      size_t bytes = 0;
+      int64_t hi = lo;
+      uint64_t segs = 0;
+      while (hi < n) {
+        const int64_t u = hi;
+        // rows already held gain the entry u when the upper end moves past u
+        size_t add = 0;
+        const int64_t ub = H.nptr[u], ue = H.nptr[u + 1];
+        for (int64_t p = ub; p < ue; p++)
+          if (mark[hc[p]] == stamp) add += 4;
+        std::vector<std::pair<int32_t, int32_t>> fresh;
+        if (mark[u] != stamp) fresh.push_back({(int32_t)u, H.dlo[u]});
+        for (int64_t p = ub; p < ub + H.dlo[u]; p++) {
+          const int32_t v = hc[p];
+          if (mark[v] == stamp) continue;
+          // row v up to and including u
+          const int32_t* rb = hc + H.nptr[v];
+          const int64_t len = std::upper_bound(rb, rb + H.dr[v], (int32_t)u) - rb;
+          fresh.push_back({v, (int32_t)len});
+        }
+        for (auto& f : fresh) add += (size_t)f.second * 4 + 32;
+        add += (size_t)H.dlo[u] * 16;  // segment descriptors
+        if (bytes + add > cap_rows && hi > lo) break;
+        bytes += add;
+        for (int64_t p = ub; p < ue; p++)
+          if (mark[hc[p]] == stamp) stored[hc[p]]++;
+        for (auto& f : fresh) {
+          mark[f.first] = stamp;
+          stored[f.first] = f.second;
+          members.push_back(f.first);
+        }
+        segs += H.dlo[u];
+        hi++;
+      }
+      if (bytes > cap_rows) throw Fail(M4_ENOMEM, "device budget below one owner's halo");
+      for (int32_t v : members) rows.push_back({v, 0, stored[v]});
+      P.ncol = upload_rows(true, 0);
+      P.row_len = rowlen;
+      P.own_lo = lo;
+      P.own_hi = hi;
+      Arena a = tmp_arena(c4_tmp);
+      c4_run(P, C, c->scal, tu, flags, a, s, c->num_cu, nullptr, big);
+      M4_HIP(hipStreamSynchronize(s));
+      P.row_len = nullptr;
+      lo = hi;
+    }
+  }
+
+  // ---- 5. closure over owner ranges (out-lists only), then the inverse
+  {
+    const size_t cap_rows = D.cap > fixed_used + 4096 ? D.cap - fixed_used - 4096 : 0;
+    int64_t lo = 0;
+    while (lo < n) {
+      rows.clear();
+      size_t bytes = 0;
+      int64_t hi = lo;
+      while (hi < n) {
+        const size_t add = (size_t)H.dplus[hi] * 4 + 28;
+        if (bytes + add > cap_rows && hi > lo) break;
+        bytes += add;
+        rows.push_back({(int32_t)hi, (int64_t)H.dlo[hi], H.dplus[hi]});
+        hi++;
+      }
+      P.ncol = upload_rows(false, 1);
+      P.own_lo = lo;
+      P.own_hi = hi;
+      closure_run(P, c->scal, flags, s);
+      M4_HIP(hipStreamSynchronize(s));
+      lo = hi;
+    }
+  }
+  finalize_run(c->scal, s);
+  M4_HIP(hipMemcpyAsync(c->scal_host, c->scal, sizeof(Scal), hipMemcpyDeviceToHost, s));
+  M4_HIP(hipStreamSynchronize(s));
+  const Scal& h = *c->scal_host;
+  if (h.status == 3) return set_error(c, M4_EOVERFLOW, "a count is >= 2^64");
+  if (h.status != 0) return set_error(c, M4_EINTERNAL, "closure consistency check failed");
+  for (int i = 0; i < 6; i++) out[i] = h.out[i];
+  if (st) {
+    for (int i = 0; i < 8; i++) st->basis[i] = h.basis[i];
+    st->intersect_steps = h.stat[ST_STEPS];
+    st->wedges = h.stat[ST_WEDGES];
+    st->cache_lookups = h.stat[ST_LOOKUPS];
+    st->cache_hits = h.stat[ST_HITS];
+    st->partitions = parts;
+    st->h2d_bytes = h2d_bytes;
+    st->halo_rows = halo_rows;
+    st->ms_total = now_ms() - t_start;
+    st->ms_h2d = t_h2d;
+  }
+  return M4_OK;
+}
 
 }  // namespace m4
-
-extern "C" int m4_count_batch(m4_ctx* ctx, const m4_batch* b, const m4_opts* o, uint64_t* out,
-                              m4_stats* st) {
-  (void)b;
-  (void)o;
-  (void)out;
-  (void)st;
-  return m4::set_error(ctx, M4_EINVAL, "batch path not available");
-}
-extern "C" int m4_server_create(m4_ctx*, uint64_t, int, m4_server** out) {
-  if (out) *out = nullptr;
-  return M4_EINVAL;
-}
-extern "C" int m4_server_submit(m4_server*, const m4_csr*, uint64_t, uint64_t*) { return M4_EINVAL; }
-extern "C" int m4_server_poll(m4_server*, m4_result*, int, int* got) {
-  if (got) *got = 0;
-  return M4_EINVAL;
-}
-extern "C" int m4_server_drain(m4_server*) { return M4_EINVAL; }
-extern "C" void m4_server_destroy(m4_server*) {}
-extern "C" double m4_server_now_ms(const m4_server*) { return 0.0; }

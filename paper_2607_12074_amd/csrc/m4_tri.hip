@@ -18,176 +18,39 @@
 // per workgroup (block-local aggregation).
 #include <limits.h>
 
-#include "m4_device.h"
+#include "m4_tri_dev.h"
 
 namespace m4 {
 
 namespace {
 
-// signature of a cached frontier: (j, slot, required-adjacency mask,
-// required-non-adjacency mask); a lookup matches only on all four fields.
-__host__ __device__ __forceinline__ uint32_t sig_key(uint32_t j, uint32_t slot, uint32_t mplus,
-                                                     uint32_t mminus) {
-  return (j << 28) | ((mplus & 0xfu) << 24) | ((mminus & 0xfu) << 20) | (slot & 0xfffffu);
-}
-
-struct TriArgs {
-  const int32_t* order;   // owners sorted by bucket
-  const int64_t* start;   // bucket ranges (device, in Scal)
-  const int64_t* nptr;
-  const int64_t* optr;
-  const int32_t* ncol;
-  const int32_t* dlo;
-  const int32_t* dplus;
-  uint32_t* t;
-  Scal* scal;
-  uint32_t flags;
-  uint32_t cache_rows;
-  int bucket;
-  int slot;  // kernel slot of the work counters
-  unsigned int* work;     // atomic owner counter for this bucket
-  // global-bitmap variant scratch (per block), sized for kmax
-  int kmax;
-  uint64_t* gbits;
-  int32_t* garr;
-};
-
-template <typename T>
-__device__ __forceinline__ T ld(const T* p, bool fresh) {
-  if (fresh) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return *p;
-}
-
-// |C(u, a[i]) & N+(a[p])| recomputed from the lists, for frontiers that are
-// not held in the signature cache.
-__device__ __forceinline__ uint64_t k4_recompute(const int32_t* ncol, const int32_t* a, int k,
-                                                 int p, int64_t si, int li, int64_t sp, int lp) {
-  uint64_t c = 0;
-  for (int jj = 0; jj < lp; jj++) {
-    int32_t x = ncol[sp + jj];
-    int64_t q = lower_index(a, (int64_t)p + 1, (int64_t)k, x);
-    if (q >= k || a[q] != x) continue;
-    int64_t r = lower_index(ncol, si, si + li, x);
-    if (r < si + li && ncol[r] == x) c++;
-  }
-  return c;
-}
-
-// One owner processed by NT threads with per-owner arrays in `a..colcnt`
-// (LDS or global) and bitmap rows of W words each in `B`.
-template <int NT, bool FRESH>
-__device__ __forceinline__ void tri_owner(const TriArgs& A, int32_t u, int32_t* a, int32_t* sst,
-                                          int32_t* soe, int32_t* slen, int32_t* spref,
-                                          uint32_t* colcnt, uint32_t* tag, uint64_t* B,
-                                          u128_t& k4acc,
-                                          unsigned long long& steps, unsigned long long& looks,
-                                          unsigned long long& hits, unsigned long long& ksum,
-                                          unsigned long long& tris) {
-  const int tid = threadIdx.x;
-  const int k = A.dplus[u];
-  const int64_t rb = A.nptr[u] + A.dlo[u];
-  const int64_t oe_u = A.optr[u];
-  const int W = (k + 63) >> 6;
-  if (tid == 0) ksum += (unsigned long long)k;
-  for (int i = tid; i < k; i += NT) {
-    int32_t v = A.ncol[rb + i];
-    a[i] = v;
-    sst[i] = (int32_t)(A.nptr[v] + A.dlo[v]);
-    soe[i] = (int32_t)A.optr[v];
-    slen[i] = A.dplus[v];
-    colcnt[i] = 0;
-  }
-  for (int i = tid; i < k * W; i += NT) B[i] = 0;
-  __syncthreads();
-  // exclusive prefix of the out-degrees of a[0..k) into spref[0..k]
-  {
-    const int per = (k + NT - 1) / NT;
-    const int lo = tid * per;
-    int64_t s = 0;
-    for (int i = lo; i < lo + per && i < k; i++) s += slen[i];
-    int64_t tot;
-    int64_t run = block_excl_scan64<NT>(s, &tot);
-    for (int i = lo; i < lo + per && i < k; i++) {
-      spref[i] = (int32_t)run;
-      run += slen[i];
-    }
-    if (tid == 0) spref[k] = (int32_t)tot;
-  }
-  __syncthreads();
-  const int total = spref[k];
-  for (int q = tid; q < total; q += NT) {
-    int i = upper_index(spref, k, q);
-    int j = q - spref[i];
-    int32_t x = A.ncol[sst[i] + j];
-    int p = (int)lower_index(a, (int64_t)i + 1, (int64_t)k, x);
-    steps++;
-    if (p < k && a[p] == x) {
-      atomicOr((unsigned long long*)&B[i * W + (p >> 6)], 1ull << (p & 63));
-      atomicAdd(&colcnt[p], 1u);
-      atomicAdd(&A.t[soe[i] + j], 1u);
-    }
-  }
-  __syncthreads();
-  // triangles on the owner's own out-edges: (u, a[i], *) and (u, *, a[i])
-  for (int i = tid; i < k; i += NT) {
-    uint32_t rc = 0;
-    for (int w = 0; w < W; w++) rc += __popcll(ld(&B[i * W + w], FRESH));
-    uint32_t c = rc + ld(&colcnt[i], FRESH);
-    tris += rc;
-    if (c) atomicAdd(&A.t[oe_u + i], c);
-  }
-  // The rows that fit the cache capacity are published with their signature
-  // (j = 2, slot i, adjacency to both embedded vertices required, no
-  // non-adjacency); other rows stay unpublished and are recomputed.
-  const bool cache_on = !(A.flags & M4_NO_CACHE);
-  const uint32_t cap = A.cache_rows ? A.cache_rows : 0xffffffffu;
-  for (int i = tid; i < k; i += NT)
-    tag[i] = (cache_on && (uint32_t)i < cap) ? sig_key(2, (uint32_t)i, 3, 0) : 0u;
-  __syncthreads();
-  // 4-cliques: for every triangle (u, a[i], a[p]) intersect the two frontiers
-  for (int i = tid; i < k; i += NT) {
-    const bool ci = tag[i] == sig_key(2, (uint32_t)i, 3, 0);
-    for (int w = 0; w < W; w++) {
-      uint64_t bits = ld(&B[i * W + w], FRESH);
-      while (bits) {
-        int p = (w << 6) + __ffsll((long long)bits) - 1;
-        bits &= bits - 1;
-        looks++;
-        const bool cp = tag[p] == sig_key(2, (uint32_t)p, 3, 0);
-        if (ci && cp) {
-          hits++;
-          uint64_t c = 0;
-          for (int ww = p >> 6; ww < W; ww++)
-            c += __popcll(ld(&B[i * W + ww], FRESH) & ld(&B[p * W + ww], FRESH));
-          k4acc += c;
-        } else {
-          k4acc += k4_recompute(A.ncol, a, k, p, sst[i], slen[i], sst[p], slen[p]);
-        }
-      }
-    }
-  }
-  __syncthreads();
-}
-
 template <int KMAX, int NT>
 __global__ __launch_bounds__(NT) void k_tri_lds(TriArgs A) {
   constexpr int WMAX = (KMAX + 63) / 64;
+  constexpr bool HASH = KMAX <= 512;  // the hash table fits beside the bitmap
+  constexpr int HSLOTS = HASH ? 2 * KMAX : 1;
   __shared__ int32_t a[KMAX], sst[KMAX], soe[KMAX], slen[KMAX], spref[KMAX + 1];
   __shared__ uint32_t colcnt[KMAX], tag[KMAX];
   __shared__ uint64_t B[KMAX * WMAX];
+  __shared__ int32_t hk[HSLOTS];
+  __shared__ int16_t hv[HSLOTS];
   __shared__ int s_item;
   const int64_t b0 = A.start[A.bucket], cnt = A.start[A.bucket + 1] - b0;
   u128_t k4 = 0;
   unsigned long long steps = 0, looks = 0, hits = 0, ksum = 0, tris = 0, owners = 0;
   for (;;) {
-    if (threadIdx.x == 0) s_item = (int)atomicAdd(A.work, 1u);
+    if (threadIdx.x == 0) s_item = (int)atomicAdd(A.work, (unsigned)A.grab);
     __syncthreads();
-    const int64_t item = s_item;
+    const int64_t first = s_item;
     __syncthreads();
-    if (item >= cnt) break;
-    tri_owner<NT, false>(A, A.order[b0 + item], a, sst, soe, slen, spref, colcnt, tag, B, k4,
-                         steps, looks, hits, ksum, tris);
-    owners++;
+    if (first >= cnt) break;
+    const int64_t last = first + A.grab < cnt ? first + A.grab : cnt;
+    for (int64_t item = first; item < last; item++) {
+      tri_owner<NT, false, false, HASH>(A, A.order[b0 + item], threadIdx.x, a, sst, soe, slen,
+                                        spref, colcnt, tag, B, k4, steps, looks, hits, ksum,
+                                        tris, hk, hv);
+      owners++;
+    }
   }
   block_add_u128<NT>(&A.scal->acc[ACC_K4], k4);
   if (A.flags & M4_STATS) {
@@ -222,7 +85,7 @@ __global__ __launch_bounds__(NT) void k_tri_global(TriArgs A) {
     const int64_t item = s_item;
     __syncthreads();
     if (item >= cnt) break;
-    tri_owner<NT, true>(A, A.order[b0 + item], a, sst, soe, slen, spref, colcnt, tag, B, k4,
+    tri_owner<NT, true>(A, A.order[b0 + item], threadIdx.x, a, sst, soe, slen, spref, colcnt, tag, B, k4,
                         steps, looks, hits, ksum, tris);
     owners++;
     __threadfence();
@@ -242,11 +105,11 @@ __global__ __launch_bounds__(NT) void k_tri_global(TriArgs A) {
 // bucket of every owner by its out-degree k
 enum { TK_NONE = 0, TK_WAVE, TK_128, TK_256, TK_512, TK_1024, TK_GLOBAL, TK_N };
 
-__global__ void k_tri_keys(const int32_t* __restrict__ dplus, int64_t n, int wave_max,
-                           uint32_t* __restrict__ key, Scal* scal) {
+__global__ void k_tri_keys(const int32_t* __restrict__ dplus, int64_t n, int64_t own_lo,
+                           int64_t own_hi, int wave_max, uint32_t* __restrict__ key, Scal* scal) {
   int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (u >= n) return;
-  int k = dplus[u];
+  int k = (u >= own_lo && u < own_hi) ? dplus[u] : 0;
   uint32_t b;
   if (k < 2) b = TK_NONE;
   else if (k <= wave_max) b = TK_WAVE;
@@ -287,7 +150,8 @@ void tri_run(const Prep& P, Scal* scal, const Tuning& tu, uint32_t flags, uint32
   if (!key || !order || !rtmp || !start) throw Fail(M4_EINTERNAL, "workspace too small (tri)");
   fill_u32(&scal->work[0], 0, 8, s);
   int wave_max = tu.tri_wave_max < 2 ? 2 : (tu.tri_wave_max > 64 ? 64 : tu.tri_wave_max);
-  k_tri_keys<<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(P.dplus, n, wave_max, key, scal);
+  k_tri_keys<<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(P.dplus, n, P.own_lo, P.hi(), wave_max,
+                                                         key, scal);
   radix_pass(key, nullptr, n, 0, 4, nullptr, order, rtmp, start, s);
   // largest out-degree of the global bucket decides its scratch size
   unsigned int kmax_g = 0;
@@ -316,6 +180,7 @@ void tri_run(const Prep& P, Scal* scal, const Tuning& tu, uint32_t flags, uint32
     A.bucket = bucket;
     A.slot = slot;
     A.work = &scal->work[bucket];
+    A.grab = KM <= 64 ? 16 : (KM <= 128 ? 4 : 1);
     int64_t blocks = (int64_t)num_cu * blocks_per_cu;
     if (blocks > hstart[bucket + 1] - hstart[bucket]) blocks = hstart[bucket + 1] - hstart[bucket];
     if (kt) kt->begin(slot, s);
@@ -338,6 +203,7 @@ void tri_run(const Prep& P, Scal* scal, const Tuning& tu, uint32_t flags, uint32
     int32_t* garr = reinterpret_cast<int32_t*>(big + bits_bytes);
     A.bucket = TK_GLOBAL;
     A.slot = M4_K_TRI_GLOBAL;
+    A.grab = 1;
     A.work = &scal->work[TK_GLOBAL];
     A.kmax = (int)K;
     A.gbits = gbits;

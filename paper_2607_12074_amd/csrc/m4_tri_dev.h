@@ -1,0 +1,237 @@
+// m4_tri_dev.h -- device routine of the triangle / 4-clique anchor for one
+// owner, shared by the single-graph kernels and the batched kernel.
+#pragma once
+#include "m4_device.h"
+
+namespace m4 {
+
+// Orders the LDS accesses of one wavefront (all lanes run in lockstep; the
+// fence keeps the compiler from moving LDS loads above earlier stores).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// signature of a cached frontier: (j, slot, required-adjacency mask,
+// required-non-adjacency mask); a lookup matches only on all four fields.
+__host__ __device__ __forceinline__ uint32_t sig_key(uint32_t j, uint32_t slot, uint32_t mplus,
+                                                     uint32_t mminus) {
+  return (j << 28) | ((mplus & 0xfu) << 24) | ((mminus & 0xfu) << 20) | (slot & 0xfffffu);
+}
+
+struct TriArgs {
+  const int32_t* order;   // owners sorted by bucket
+  const int64_t* start;   // bucket ranges (device, in Scal)
+  const int64_t* nptr;
+  const int64_t* optr;
+  const int32_t* ncol;
+  const int32_t* dlo;
+  const int32_t* dplus;
+  uint32_t* t;
+  Scal* scal;
+  uint32_t flags;
+  uint32_t cache_rows;
+  int bucket;
+  int slot;  // kernel slot of the work counters
+  int grab;  // owners taken per atomic on the work counter
+  unsigned int* work;     // atomic owner counter for this bucket
+  // global-bitmap variant scratch (per block), sized for kmax
+  int kmax;
+  uint64_t* gbits;
+  int32_t* garr;
+};
+
+template <typename T>
+__device__ __forceinline__ T ld(const T* p, bool fresh) {
+  if (fresh) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return *p;
+}
+
+// |C(u, a[i]) & N+(a[p])| recomputed from the lists, for frontiers that are
+// not held in the signature cache.
+__device__ __forceinline__ uint64_t k4_recompute(const int32_t* ncol, const int32_t* a, int k,
+                                                 int p, int64_t si, int li, int64_t sp, int lp) {
+  uint64_t c = 0;
+  for (int jj = 0; jj < lp; jj++) {
+    int32_t x = ncol[sp + jj];
+    int64_t q = lower_index(a, (int64_t)p + 1, (int64_t)k, x);
+    if (q >= k || a[q] != x) continue;
+    int64_t r = lower_index(ncol, si, si + li, x);
+    if (r < si + li && ncol[r] == x) c++;
+  }
+  return c;
+}
+
+#define TRI_SYNC()                \
+  do {                            \
+    if (WAVE_ONLY) wave_sync();   \
+    else __syncthreads();         \
+  } while (0)
+
+// One owner processed by NT threads with per-owner arrays in `a..colcnt`
+// (LDS or global) and bitmap rows of W words each in `B`.
+// HASH: positions of the out-list are found through an LDS hash table
+// (hk/hv, 2H >= 2k slots) instead of a binary search over a[].
+template <int NT, bool FRESH, bool WAVE_ONLY = false, bool HASH = false>
+__device__ __forceinline__ void tri_owner(const TriArgs& A, int32_t u, const int tid, int32_t* a,
+                                          int32_t* sst,
+                                          int32_t* soe, int32_t* slen, int32_t* spref,
+                                          uint32_t* colcnt, uint32_t* tag, uint64_t* B,
+                                          u128_t& k4acc,
+                                          unsigned long long& steps, unsigned long long& looks,
+                                          unsigned long long& hits, unsigned long long& ksum,
+                                          unsigned long long& tris, int32_t* hk = nullptr,
+                                          int16_t* hv = nullptr) {
+  const int k = A.dplus[u];
+  const int64_t rb = A.nptr[u] + A.dlo[u];
+  const int64_t oe_u = A.optr[u];
+  const int W = (k + 63) >> 6;
+  if (tid == 0) ksum += (unsigned long long)k;
+  for (int i = tid; i < k; i += NT) {
+    int32_t v = A.ncol[rb + i];
+    a[i] = v;
+    sst[i] = (int32_t)(A.nptr[v] + A.dlo[v]);
+    soe[i] = (int32_t)A.optr[v];
+    slen[i] = A.dplus[v];
+    colcnt[i] = 0;
+  }
+  for (int i = tid; i < k * W; i += NT) B[i] = 0;
+  int H = 16, hshift = 28;
+  if (HASH) {
+    while (H < 2 * k) {
+      H <<= 1;
+      hshift--;
+    }
+    for (int i = tid; i < H; i += NT) hk[i] = -1;
+  }
+  TRI_SYNC();
+  if (HASH) {
+    for (int i = tid; i < k; i += NT) {
+      const int32_t key = a[i];
+      uint32_t h = ((uint32_t)key * 0x9E3779B1u) >> hshift;
+      while (atomicCAS(&hk[h], -1, key) != -1) h = (h + 1) & (uint32_t)(H - 1);
+      hv[h] = (int16_t)i;
+    }
+  }
+  // exclusive prefix of the out-degrees of a[0..k) into spref[0..k]
+  {
+    const int per = (k + NT - 1) / NT;
+    const int lo = tid * per;
+    int64_t s = 0;
+    for (int i = lo; i < lo + per && i < k; i++) s += slen[i];
+    int64_t tot;
+    int64_t run = block_excl_scan64<NT>(s, &tot);
+    for (int i = lo; i < lo + per && i < k; i++) {
+      spref[i] = (int32_t)run;
+      run += slen[i];
+    }
+    if (tid == 0) spref[k] = (int32_t)tot;
+  }
+  TRI_SYNC();
+  const int total = spref[k];
+  // Flattened (row, element) pairs: thread tid takes q = tid, tid + NT, ...;
+  // the row index only moves forward, and four element loads are issued
+  // before the four lookups so that their latencies overlap.
+  int i = tid < total ? upper_index(spref, k, tid) : 0;
+  int ii[4], jj[4];
+  int32_t xx[4];
+  // loads of the next batch are issued before the lookups of the current one
+  auto fetch = [&](int q0) {
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+      const int q = q0 + r * NT;
+      ii[r] = -1;
+      if (q < total) {
+        while (spref[i + 1] <= q) i++;
+        ii[r] = i;
+        jj[r] = q - spref[i];
+        xx[r] = A.ncol[sst[i] + jj[r]];
+      }
+    }
+  };
+  fetch(tid);
+  for (int q0 = tid; q0 < total; q0 += 4 * NT) {
+    int ci[4], cj[4];
+    int32_t cx[4];
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+      ci[r] = ii[r];
+      cj[r] = jj[r];
+      cx[r] = xx[r];
+    }
+    if (q0 + 4 * NT < total) fetch(q0 + 4 * NT);
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+      if (ci[r] < 0) continue;
+      const int ir = ci[r];
+      const int32_t x = cx[r];
+      int p;
+      if (HASH) {
+        // x > a[ir], so a hit is always a position after ir
+        uint32_t h = ((uint32_t)x * 0x9E3779B1u) >> hshift;
+        p = -1;
+        for (;;) {
+          const int32_t key = hk[h];
+          if (key == x) {
+            p = hv[h];
+            break;
+          }
+          if (key == -1) break;
+          h = (h + 1) & (uint32_t)(H - 1);
+        }
+      } else {
+        p = (int)lower_index(a, (int64_t)ir + 1, (int64_t)k, x);
+        if (p >= k || a[p] != x) p = -1;
+      }
+      steps++;
+      if (p >= 0) {
+        atomicOr((unsigned long long*)&B[ir * W + (p >> 6)], 1ull << (p & 63));
+        atomicAdd(&colcnt[p], 1u);
+        atomicAdd(&A.t[soe[ir] + cj[r]], 1u);
+      }
+    }
+  }
+  TRI_SYNC();
+  // triangles on the owner's own out-edges: (u, a[i], *) and (u, *, a[i])
+  for (int i = tid; i < k; i += NT) {
+    uint32_t rc = 0;
+    for (int w = 0; w < W; w++) rc += __popcll(ld(&B[i * W + w], FRESH));
+    uint32_t c = rc + ld(&colcnt[i], FRESH);
+    tris += rc;
+    if (c) atomicAdd(&A.t[oe_u + i], c);
+  }
+  // The rows that fit the cache capacity are published with their signature
+  // (j = 2, slot i, adjacency to both embedded vertices required, no
+  // non-adjacency); other rows stay unpublished and are recomputed.
+  const bool cache_on = !(A.flags & M4_NO_CACHE);
+  const uint32_t cap = A.cache_rows ? A.cache_rows : 0xffffffffu;
+  for (int i = tid; i < k; i += NT)
+    tag[i] = (cache_on && (uint32_t)i < cap) ? sig_key(2, (uint32_t)i, 3, 0) : 0u;
+  TRI_SYNC();
+  // 4-cliques: for every triangle (u, a[i], a[p]) intersect the two frontiers
+  for (int i = tid; i < k; i += NT) {
+    const bool ci = tag[i] == sig_key(2, (uint32_t)i, 3, 0);
+    for (int w = 0; w < W; w++) {
+      uint64_t bits = ld(&B[i * W + w], FRESH);
+      while (bits) {
+        int p = (w << 6) + __ffsll((long long)bits) - 1;
+        bits &= bits - 1;
+        looks++;
+        const bool cp = tag[p] == sig_key(2, (uint32_t)p, 3, 0);
+        if (ci && cp) {
+          hits++;
+          uint64_t c = 0;
+          for (int ww = p >> 6; ww < W; ww++)
+            c += __popcll(ld(&B[i * W + ww], FRESH) & ld(&B[p * W + ww], FRESH));
+          k4acc += c;
+        } else {
+          k4acc += k4_recompute(A.ncol, a, k, p, sst[i], slen[i], sst[p], slen[p]);
+        }
+      }
+    }
+  }
+  TRI_SYNC();
+}
+
+
+}  // namespace m4
