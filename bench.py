@@ -26,16 +26,20 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "edges/s for exact induced 4-motif counts; batched graphs/s vs plain; p99 ms"
 
-# Algorithmic bytes of one launch of each kernel slot, from the work counters
-# the library reports (see m4_stats in include/m4.h):
-#   triangle slots  4 E + 36 K + 8 T + 24 R   (E list elements looked up,
-#                   K out-list entries of the owners -- the entry itself plus
-#                   24 B of row metadata and 8 B of t update each, T triangles
-#                   -- one t update of 8 B each, R owners -- 24 B of metadata)
-#   4-cycle windows 4 E + 24 S + 16 R         (E wedge endpoints, S lower
-#                   neighbours -- entry plus 20 B of row metadata, R owners)
-#   4-cycle hash    4 X + 16 S + 16 R         (X row entries read)
-#   closure         12 m + 28 n
+# Algorithmic bytes of one launch of each kernel slot: what the method must
+# stream from HBM per unit of work, a function of the graph and the degree
+# order only (not of this implementation), times the units that launch
+# processed (work counters of m4_stats, include/m4.h):
+#   triangle + 4-clique slots  4 E + 4 K + 8 R + 4 W
+#       E  out-list elements of the owners' out-neighbours (each oriented
+#          edge u->v streams N+(v)), K  the owners' own out-list entries,
+#       R  owners (one 8-byte row offset each), W  sum over the triangles
+#          (u, v, w) of |N+(w)| (the list a 4-clique step intersects)
+#   4-cycle slots (window, hash)  4 X + 8 S + 8 R
+#       X  wedge endpoints (the prefix below the owner of each lower
+#          neighbour's row), S  lower neighbours (row offset), R  owners
+#   closure  12 m + 4 n  (per oriented edge its head, t_e and the head's
+#          degree; per vertex its degree)
 TRI_SLOTS = {1: "tri_global", 2: "tri_1024", 3: "tri_512", 4: "tri_256", 5: "tri_128",
              6: "tri_wave"}
 KERNEL_SYMBOL = {
@@ -52,13 +56,11 @@ def alg_bytes(slot: int, st: dict, n: int, m: int) -> float:
     E, R, A, A2 = (st["k_elems"][slot], st["k_rows"][slot], st["k_aux"][slot],
                    st["k_aux2"][slot])
     if slot in TRI_SLOTS:
-        return 4.0 * E + 36.0 * A + 8.0 * A2 + 24.0 * R
-    if slot in (8, 9):
-        return 4.0 * E + 24.0 * A + 16.0 * R
-    if slot == 10:
-        return 4.0 * A2 + 16.0 * A + 16.0 * R
+        return 4.0 * E + 4.0 * A + 8.0 * R + 4.0 * A2
+    if slot in (8, 9, 10):
+        return 4.0 * E + 8.0 * A + 8.0 * R
     if slot == 11:
-        return 12.0 * m + 28.0 * n
+        return 12.0 * m + 4.0 * n
     return float("nan")
 
 
@@ -101,6 +103,12 @@ def run_batch_leg(ctx, args):
     gen_s = time.perf_counter() - t0
     dev = [torch.from_numpy(a).cuda() for a in arena]
     sum_m = int(arena[1][-1]) // 2
+    # thresholds of the fused launch picked by the autotuner on a sample of
+    # the same distribution (other seed), outside the timed region
+    sample = m4.pack_batch([gg.batch_graph(i, seed=13) for i in range(512)])
+    t0 = time.perf_counter()
+    tuning = ctx.autotune(batch=sample, reps=2)
+    tune_s = time.perf_counter() - t0
     out = ctx.count_batch(*dev)  # plan + capture
     for _ in range(2):
         ctx.count_batch(*dev)
@@ -122,7 +130,9 @@ def run_batch_leg(ctx, args):
             "graphs_per_s": G / (ms_batch * 1e-3), "edges_per_s": sum_m / (ms_batch * 1e-3),
             "plain_ms": ms_plain, "plain_graphs_per_s": G / (ms_plain * 1e-3),
             "speedup_vs_plain": ms_plain / ms_batch,
-            "plain_equal": bool(np.array_equal(plain, out)), "gen_s": round(gen_s, 2)}
+            "plain_equal": bool(np.array_equal(plain, out)), "gen_s": round(gen_s, 2),
+            "tuning": {k: tuning[k] for k in ("batch_variant", "batch_light")},
+            "tune_s": round(tune_s, 2)}
 
 
 def run_serve_leg(ctx, args):
@@ -141,11 +151,14 @@ def run_serve_leg(ctx, args):
     gen_s = time.perf_counter() - t0
     budget = int(args.serve_budget_gb * (1 << 30))
 
-    def collect(srv, ids):
+    def collect(srv, ids, limit_s=300.0):
         got = {}
+        t_end = time.perf_counter() + limit_s
         while len(got) < len(ids):
             for r in srv.poll(1024):
                 got[r["id"]] = r
+            if time.perf_counter() > t_end:
+                raise TimeoutError(f"serving leg: {len(got)} of {len(ids)} results")
             time.sleep(0.0002)
         return [got[i] for i in ids]
 
@@ -158,6 +171,7 @@ def run_serve_leg(ctx, args):
     ids = [srv.submit(*g, tag=i) for i, g in enumerate(graphs)]
     closed = collect(srv, ids)
     sat = R / (time.perf_counter() - t0)
+    note(f"serving closed loop: {sat:.1f} graphs/s")
     rate = 0.7 * sat
     gaps = np.random.default_rng(7).exponential(1.0 / rate, R)
     ids = []
@@ -184,6 +198,11 @@ def run_serve_leg(ctx, args):
             "p99_ms": float(np.percentile(lat, 99)), "budget_bytes": budget,
             "max_inflight_bytes": st["max_inflight_bytes"], "launches": st["launches"],
             "mix_equals_closed_loop": bool(same), "gen_s": round(gen_s, 2)}
+
+
+def note(msg):
+    """One progress line per finished stage, on stderr."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
 def make_workload(args):
@@ -222,6 +241,7 @@ def main():
 
     rp, col, gen_s = make_workload(args)
     n, m = len(rp) - 1, len(col) // 2
+    note(f"workload n={n} m={m} generated in {gen_s:.1f} s")
     dev = torch.device("cuda:0")
     rp_d = torch.from_numpy(rp).to(dev)
     col_d = torch.from_numpy(col).to(dev)
@@ -239,6 +259,7 @@ def main():
     for _ in range(args.warmup):
         counts = ctx.count(rp_d, col_d)
     torch.cuda.synchronize()
+    note("warmup done")
 
     # timed region: K full counts, per-kernel HIP events on the launch stream
     ms_k = np.zeros(m4.M4_NK)
@@ -251,6 +272,7 @@ def main():
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / max(args.steps, 1)
     ms_k /= max(args.steps, 1)
+    note(f"timed {args.steps} steps: {ms_step:.3f} ms/step")
 
     # work counters (outside the timed region; they do not depend on timing)
     counts2, st = ctx.count(rp_d, col_d, stats=True)
@@ -276,9 +298,15 @@ def main():
                "kind": "oracle",
                "sample": f"whole workload graph (n={n}, m={m}), plain closure counter, "
                          f"{cpu_s:.1f} s"}
+        note(f"cpu oracle: {cpu_s:.1f} s, parity {parity}")
 
     batched = run_batch_leg(ctx, args) if args.batch_graphs > 0 else None
+    if batched:
+        note(f"batched leg: {batched['graphs_per_s']:.0f} graphs/s, "
+             f"{batched['speedup_vs_plain']:.2f}x plain")
     serving = run_serve_leg(ctx, args) if args.serve_requests > 0 else None
+    if serving:
+        note(f"serving leg: p99 {serving['p99_ms']:.2f} ms")
 
     line = {
         "metric": METRIC,

@@ -103,7 +103,8 @@ enum {
  * with a non-NULL m4_stats; the k_* counters need M4_STATS and ms_kernel[]
  * needs M4_TIMING.  Per slot:
  *   triangle slots: k_elems = list elements looked up, k_rows = owners,
- *                   k_aux = out-list entries of the owners, k_aux2 = triangles
+ *                   k_aux = out-list entries of the owners, k_aux2 = sum over
+ *                   the triangles (u, v, w), u < v < w, of |N+(w)|
  *   4-cycle slots:  k_elems = wedge endpoints counted, k_rows = owners,
  *                   k_aux = lower neighbours (segments), k_aux2 = segment
  *                   visits (window slots) or row entries read (hash slot)
@@ -134,6 +135,9 @@ int m4_ctx_create(int device, m4_ctx** out);
 void m4_ctx_destroy(m4_ctx* ctx);
 /* Text of the last error raised in this context (never NULL). */
 const char* m4_last_error(const m4_ctx* ctx);
+/* Architecture name and compute-unit count of the context's device, e.g.
+ * "gfx950:sramecc+:xnack- 256 CU" (owned by the context, never NULL). */
+const char* m4_ctx_device(const m4_ctx* ctx);
 const char* m4_strerror(int status);
 
 /* Blocking count on device 0 with a process-wide default context. */
@@ -150,6 +154,32 @@ int m4_count_motifs4_ex(m4_ctx* ctx, const m4_csr* g, const m4_opts* opts,
 int m4_edge_triangles(m4_ctx* ctx, const m4_csr* g, const m4_opts* opts,
                       uint32_t* t_out);
 
+/* --------------------------------------------------------------- tuning --
+ * Degree-bucket and tile thresholds of a context.  They move owners between
+ * kernels and never change a count.  m4_autotune times every candidate on
+ * the given sample (a graph for the single-graph path and/or an arena for
+ * the fused batched launch, reps timed runs each after one warm run), checks
+ * that all candidates agree on every count (else M4_EINTERNAL), keeps the
+ * fastest in the context and returns it in out (may be NULL).  On error the
+ * context's tuning is unchanged. */
+typedef struct {
+  int32_t tri_wave_max;  /* single graph: owners with out-degree <= this use one
+                            64-thread workgroup (2..64, default 64)            */
+  int32_t c4_light_max;  /* single graph: owners with wedge bound <= this use the
+                            LDS hash (1..2048, default 2048)                   */
+  int32_t batch_variant; /* fused batched kernel: 0 = 1024 threads with 96 KiB of
+                            LDS tiles (out-degrees up to 768), 1 = 512 threads
+                            with 40 KiB (up to 448); default 0                 */
+  int32_t batch_light;   /* fused batched kernel: wedge bound of the per-
+                            wavefront 4-cycle hash (1..256, default 128)      */
+  int32_t reserved[4];
+} m4_tuning;
+
+int m4_get_tuning(const m4_ctx* ctx, m4_tuning* out);
+int m4_set_tuning(m4_ctx* ctx, const m4_tuning* t);
+int m4_autotune(m4_ctx* ctx, const m4_csr* graph, const struct m4_batch_s* batch, int reps,
+                m4_tuning* out);
+
 /* ---------------------------------------------------------------- batch --
  * Many independent graphs packed in one arena: graph i has vertices
  * [voff[i], voff[i+1]) and CSR entries [eoff[i], eoff[i+1]) of row_ptr/col;
@@ -160,7 +190,7 @@ int m4_edge_triangles(m4_ctx* ctx, const m4_csr* g, const m4_opts* opts,
  *   col    : int32[eoff[G]]      -- graph i uses col[eoff[i] ... eoff[i+1])
  * All arrays live on the device when on_device, else on the host.  out is a
  * host array of G * 6 counts.  One persistent launch counts every graph. */
-typedef struct {
+typedef struct m4_batch_s {
   int64_t num_graphs;
   const int64_t* voff;    /* int64[G+1] */
   const int64_t* eoff;    /* int64[G+1] */

@@ -74,6 +74,15 @@ class Batch(ctypes.Structure):
                 ("col", ctypes.c_void_p), ("on_device", ctypes.c_int32)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("tri_wave_max", ctypes.c_int32), ("c4_light_max", ctypes.c_int32),
+                ("batch_variant", ctypes.c_int32), ("batch_light", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
+
+    def to_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_[:4]}
+
+
 class Result(ctypes.Structure):
     _fields_ = [("id", ctypes.c_uint64), ("tag", ctypes.c_uint64), ("status", ctypes.c_int32),
                 ("counts", ctypes.c_uint64 * 6), ("t_submit_ms", ctypes.c_double),
@@ -103,6 +112,8 @@ def lib():
         L.m4_ctx_destroy.restype = None
         L.m4_last_error.argtypes = [p]
         L.m4_last_error.restype = ctypes.c_char_p
+        L.m4_ctx_device.argtypes = [p]
+        L.m4_ctx_device.restype = ctypes.c_char_p
         L.m4_strerror.argtypes = [i]
         L.m4_strerror.restype = ctypes.c_char_p
         L.m4_count_motifs4.argtypes = [ctypes.POINTER(Csr), p]
@@ -111,6 +122,10 @@ def lib():
         L.m4_edge_triangles.argtypes = [p, ctypes.POINTER(Csr), ctypes.POINTER(Opts), p]
         L.m4_count_batch.argtypes = [p, ctypes.POINTER(Batch), ctypes.POINTER(Opts), p,
                                      ctypes.POINTER(Stats)]
+        L.m4_get_tuning.argtypes = [p, ctypes.POINTER(Tuning)]
+        L.m4_set_tuning.argtypes = [p, ctypes.POINTER(Tuning)]
+        L.m4_autotune.argtypes = [p, ctypes.POINTER(Csr), ctypes.POINTER(Batch), i,
+                                  ctypes.POINTER(Tuning)]
         L.m4_server_create.argtypes = [p, u64, i, ctypes.POINTER(p)]
         L.m4_server_submit.argtypes = [p, ctypes.POINTER(Csr), u64, ctypes.POINTER(u64)]
         L.m4_server_poll.argtypes = [p, ctypes.POINTER(Result), i, ctypes.POINTER(i)]
@@ -174,6 +189,7 @@ class Context:
             raise M4Error(rc, "m4_ctx_create: " + lib().m4_strerror(rc).decode())
         self.h = h
         self.device = device
+        self.arch = lib().m4_ctx_device(h).decode()
 
     def close(self):
         if getattr(self, "h", None):
@@ -231,30 +247,87 @@ class Context:
         self._check(lib().m4_edge_triangles(self.h, ctypes.byref(g), ctypes.byref(o), ptr))
         return t[: g.nnz]
 
+    def get_tuning(self) -> dict:
+        t = Tuning()
+        self._check(lib().m4_get_tuning(self.h, ctypes.byref(t)))
+        return t.to_dict()
+
+    def set_tuning(self, **kw):
+        t = Tuning()
+        self._check(lib().m4_get_tuning(self.h, ctypes.byref(t)))
+        for k, v in kw.items():
+            setattr(t, k, int(v))
+        self._check(lib().m4_set_tuning(self.h, ctypes.byref(t)))
+
+    def autotune(self, graph=None, batch=None, reps=3, cache=None) -> dict:
+        """Times the threshold candidates on a sample graph (row_ptr, col)
+        and/or a packed arena (voff, eoff, row_ptr, col) and keeps the fastest
+        in this context.  With cache (a JSON path) a result stored for the
+        same device and sample size class is reused instead of re-timing."""
+        import json
+        key = None
+        if cache is not None:
+            key = self._tune_key(graph, batch)
+            try:
+                store = json.load(open(cache))
+            except (OSError, ValueError):
+                store = {}
+            if key in store:
+                self.set_tuning(**store[key])
+                return dict(store[key], cached=True)
+        keep = _Keep()
+        g = make_csr(*graph, keep) if graph is not None else None
+        b = self._make_batch(*batch, keep=keep) if batch is not None else None
+        t = Tuning()
+        self._check(lib().m4_autotune(self.h, ctypes.byref(g) if g is not None else None,
+                                      ctypes.byref(b) if b is not None else None, int(reps),
+                                      ctypes.byref(t)))
+        res = t.to_dict()
+        if cache is not None:
+            try:
+                store = json.load(open(cache))
+            except (OSError, ValueError):
+                store = {}
+            store[key] = res
+            with open(cache, "w") as fh:
+                json.dump(store, fh, indent=1, sort_keys=True)
+        return dict(res, cached=False)
+
+    def _tune_key(self, graph, batch):
+        import math
+        parts = [self.arch]
+        if graph is not None:
+            n, nnz = len(graph[0]) - 1, len(graph[1])
+            parts.append(f"g{int(math.log2(max(n, 1)))}.{int(math.log2(max(nnz, 1)))}")
+        if batch is not None:
+            G, nnz = len(batch[0]) - 1, int(batch[1][-1])
+            parts.append(f"b{int(math.log2(max(G, 1)))}.{int(math.log2(max(nnz, 1)))}")
+        return "/".join(parts)
+
+    def _make_batch(self, voff, eoff, row_ptr, col, keep):
+        if _is_torch(row_ptr):
+            import torch
+            arrs = [voff.to(torch.int64).contiguous(), eoff.to(torch.int64).contiguous(),
+                    row_ptr.to(torch.int64).contiguous(), col.to(torch.int32).contiguous()]
+            keep.refs += arrs
+            return Batch(len(voff) - 1, *[a.data_ptr() for a in arrs],
+                         1 if row_ptr.is_cuda else 0)
+        arrs = [np.ascontiguousarray(voff, dtype=np.int64),
+                np.ascontiguousarray(eoff, dtype=np.int64),
+                np.ascontiguousarray(row_ptr, dtype=np.int64),
+                np.ascontiguousarray(col, dtype=np.int32)]
+        if arrs[3].size == 0:
+            arrs[3] = np.zeros(1, dtype=np.int32)
+        keep.refs += arrs
+        return Batch(len(voff) - 1, *[a.ctypes.data for a in arrs], 0)
+
     def count_batch(self, voff, eoff, row_ptr, col, *, flags=0, stream=None, stats=False,
                     tri_wave_max=0, c4_light_max=0, plain=False):
         """Counts of every graph of a packed arena (see m4_batch in m4.h);
         returns a (G, 6) uint64 numpy array."""
         keep = _Keep()
         G = len(voff) - 1
-        if _is_torch(row_ptr):
-            import torch
-            arrs = [voff.to(torch.int64).contiguous(), eoff.to(torch.int64).contiguous(),
-                    row_ptr.to(torch.int64).contiguous(), col.to(torch.int32).contiguous()]
-            keep.refs += arrs
-            ptrs = [a.data_ptr() for a in arrs]
-            on_dev = 1 if row_ptr.is_cuda else 0
-        else:
-            arrs = [np.ascontiguousarray(voff, dtype=np.int64),
-                    np.ascontiguousarray(eoff, dtype=np.int64),
-                    np.ascontiguousarray(row_ptr, dtype=np.int64),
-                    np.ascontiguousarray(col, dtype=np.int32)]
-            if arrs[3].size == 0:
-                arrs[3] = np.zeros(1, dtype=np.int32)
-            keep.refs += arrs
-            ptrs = [a.ctypes.data for a in arrs]
-            on_dev = 0
-        b = Batch(G, *ptrs, on_dev)
+        b = self._make_batch(voff, eoff, row_ptr, col, keep)
         if plain:
             flags |= M4_PLAIN_LOOP
         o = make_opts(flags | (M4_STATS if stats else 0), 0, 0,

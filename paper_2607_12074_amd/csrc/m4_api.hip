@@ -107,7 +107,7 @@ extern "C" int m4_ctx_create(int device, m4_ctx** out) {
     hipDeviceProp_t prop;
     M4_HIP(hipGetDeviceProperties(&prop, device));
     c->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
-    c->arch = prop.gcnArchName;
+    c->arch = std::string(prop.gcnArchName) + " " + std::to_string(c->num_cu) + " CU";
     M4_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
     M4_HIP(hipMalloc((void**)&c->scal, sizeof(Scal)));
     M4_HIP(hipHostMalloc((void**)&c->scal_host, sizeof(Scal), hipHostMallocDefault));
@@ -148,6 +148,8 @@ extern "C" void m4_ctx_destroy(m4_ctx* c) {
 extern "C" const char* m4_last_error(const m4_ctx* c) {
   return c ? c->last_error.c_str() : "no context";
 }
+
+extern "C" const char* m4_ctx_device(const m4_ctx* c) { return c ? c->arch.c_str() : "no context"; }
 
 extern "C" const char* m4_strerror(int st) {
   switch (st) {

@@ -37,7 +37,7 @@ __global__ __launch_bounds__(NT) void k_tri_lds(TriArgs A) {
   __shared__ int s_item;
   const int64_t b0 = A.start[A.bucket], cnt = A.start[A.bucket + 1] - b0;
   u128_t k4 = 0;
-  unsigned long long steps = 0, looks = 0, hits = 0, ksum = 0, tris = 0, owners = 0;
+  unsigned long long steps = 0, looks = 0, hits = 0, ksum = 0, wstream = 0, owners = 0;
   for (;;) {
     if (threadIdx.x == 0) s_item = (int)atomicAdd(A.work, (unsigned)A.grab);
     __syncthreads();
@@ -48,7 +48,7 @@ __global__ __launch_bounds__(NT) void k_tri_lds(TriArgs A) {
     for (int64_t item = first; item < last; item++) {
       tri_owner<NT, false, false, HASH>(A, A.order[b0 + item], threadIdx.x, a, sst, soe, slen,
                                         spref, colcnt, tag, B, k4, steps, looks, hits, ksum,
-                                        tris, hk, hv);
+                                        wstream, hk, hv);
       owners++;
     }
   }
@@ -60,7 +60,7 @@ __global__ __launch_bounds__(NT) void k_tri_lds(TriArgs A) {
     block_add_u64<NT>(&A.scal->kstat[A.slot][0], steps);
     block_add_u64<NT>(&A.scal->kstat[A.slot][1], threadIdx.x == 0 ? owners : 0);
     block_add_u64<NT>(&A.scal->kstat[A.slot][2], ksum);
-    block_add_u64<NT>(&A.scal->kstat[A.slot][3], tris);
+    block_add_u64<NT>(&A.scal->kstat[A.slot][3], wstream);
   }
 }
 
@@ -78,7 +78,7 @@ __global__ __launch_bounds__(NT) void k_tri_global(TriArgs A) {
   uint32_t* colcnt = (uint32_t*)(base + 5 * K + 1);
   uint32_t* tag = (uint32_t*)(base + 6 * K + 1);
   u128_t k4 = 0;
-  unsigned long long steps = 0, looks = 0, hits = 0, ksum = 0, tris = 0, owners = 0;
+  unsigned long long steps = 0, looks = 0, hits = 0, ksum = 0, wstream = 0, owners = 0;
   for (;;) {
     if (threadIdx.x == 0) s_item = (int)atomicAdd(A.work, 1u);
     __syncthreads();
@@ -86,7 +86,7 @@ __global__ __launch_bounds__(NT) void k_tri_global(TriArgs A) {
     __syncthreads();
     if (item >= cnt) break;
     tri_owner<NT, true>(A, A.order[b0 + item], threadIdx.x, a, sst, soe, slen, spref, colcnt, tag, B, k4,
-                        steps, looks, hits, ksum, tris);
+                        steps, looks, hits, ksum, wstream);
     owners++;
     __threadfence();
   }
@@ -98,7 +98,7 @@ __global__ __launch_bounds__(NT) void k_tri_global(TriArgs A) {
     block_add_u64<NT>(&A.scal->kstat[A.slot][0], steps);
     block_add_u64<NT>(&A.scal->kstat[A.slot][1], threadIdx.x == 0 ? owners : 0);
     block_add_u64<NT>(&A.scal->kstat[A.slot][2], ksum);
-    block_add_u64<NT>(&A.scal->kstat[A.slot][3], tris);
+    block_add_u64<NT>(&A.scal->kstat[A.slot][3], wstream);
   }
 }
 

@@ -72,6 +72,9 @@ __device__ __forceinline__ uint64_t k4_recompute(const int32_t* ncol, const int3
 // (LDS or global) and bitmap rows of W words each in `B`.
 // HASH: positions of the out-list are found through an LDS hash table
 // (hk/hv, 2H >= 2k slots) instead of a binary search over a[].
+// Work counters: steps (out-list elements looked up), looks/hits (frontier
+// cache), ksum (out-list entries of the owner), wstream (sum over the
+// triangles (u, v, w) of |N+(w)|, the list a merge-based 4-clique step reads).
 template <int NT, bool FRESH, bool WAVE_ONLY = false, bool HASH = false>
 __device__ __forceinline__ void tri_owner(const TriArgs& A, int32_t u, const int tid, int32_t* a,
                                           int32_t* sst,
@@ -80,7 +83,7 @@ __device__ __forceinline__ void tri_owner(const TriArgs& A, int32_t u, const int
                                           u128_t& k4acc,
                                           unsigned long long& steps, unsigned long long& looks,
                                           unsigned long long& hits, unsigned long long& ksum,
-                                          unsigned long long& tris, int32_t* hk = nullptr,
+                                          unsigned long long& wstream, int32_t* hk = nullptr,
                                           int16_t* hv = nullptr) {
   const int k = A.dplus[u];
   const int64_t rb = A.nptr[u] + A.dlo[u];
@@ -197,7 +200,6 @@ __device__ __forceinline__ void tri_owner(const TriArgs& A, int32_t u, const int
     uint32_t rc = 0;
     for (int w = 0; w < W; w++) rc += __popcll(ld(&B[i * W + w], FRESH));
     uint32_t c = rc + ld(&colcnt[i], FRESH);
-    tris += rc;
     if (c) atomicAdd(&A.t[oe_u + i], c);
   }
   // The rows that fit the cache capacity are published with their signature
@@ -217,6 +219,7 @@ __device__ __forceinline__ void tri_owner(const TriArgs& A, int32_t u, const int
         int p = (w << 6) + __ffsll((long long)bits) - 1;
         bits &= bits - 1;
         looks++;
+        wstream += (unsigned long long)slen[p];
         const bool cp = tag[p] == sig_key(2, (uint32_t)p, 3, 0);
         if (ci && cp) {
           hits++;

@@ -1,0 +1,152 @@
+// m4_tune.hip -- autotuner of the degree-bucket and tile thresholds.
+//
+// Candidate settings are timed on a caller-supplied sample (a graph for the
+// single-graph path, an arena for the fused batched launch); the fastest is
+// kept in the context.  Every candidate must give the same counts -- the
+// thresholds only move owners between kernels -- and a disagreement is an
+// internal error, not a tuning choice.
+#include <string.h>
+
+#include <chrono>
+#include <vector>
+
+#include "m4_ctx.h"
+
+namespace m4 {
+int count_batch_impl(m4_ctx* c, const m4_batch* b, const m4_opts* o, uint64_t* out,
+                     m4_stats* st);
+}
+
+using namespace m4;
+
+namespace {
+
+double wall_ms() {
+  return std::chrono::duration<double, std::milli>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+void to_public(const Tuning& t, m4_tuning* out) {
+  memset(out, 0, sizeof(*out));
+  out->tri_wave_max = t.tri_wave_max;
+  out->c4_light_max = t.c4_light_max;
+  out->batch_variant = t.batch_variant;
+  out->batch_light = t.batch_light;
+}
+
+}  // namespace
+
+extern "C" int m4_get_tuning(const m4_ctx* ctx, m4_tuning* out) {
+  if (!ctx || !out) return M4_EINVAL;
+  to_public(ctx->tune, out);
+  return M4_OK;
+}
+
+extern "C" int m4_set_tuning(m4_ctx* ctx, const m4_tuning* t) {
+  if (!ctx || !t) return M4_EINVAL;
+  if (t->tri_wave_max < 2 || t->tri_wave_max > 64 || t->c4_light_max < 1 ||
+      t->c4_light_max > C4_HASH_SLOTS / 2 || (t->batch_variant != 0 && t->batch_variant != 1) ||
+      t->batch_light < 1 || t->batch_light > 256)
+    return set_error(ctx, M4_EINVAL, "tuning value out of range");
+  ctx->tune.tri_wave_max = t->tri_wave_max;
+  ctx->tune.c4_light_max = t->c4_light_max;
+  ctx->tune.batch_variant = t->batch_variant;
+  ctx->tune.batch_light = t->batch_light;
+  return M4_OK;
+}
+
+extern "C" int m4_autotune(m4_ctx* ctx, const m4_csr* graph, const m4_batch* batch, int reps,
+                           m4_tuning* out) {
+  if (!ctx || (!graph && !batch)) return M4_EINVAL;
+  if (reps < 1) reps = 3;
+  const Tuning start = ctx->tune;
+  Tuning best = start;
+  try {
+    if (graph) {
+      const int waves[] = {16, 32, 64};
+      const int lights[] = {256, 512, 1024, 2048};
+      uint64_t ref[6];
+      bool have_ref = false;
+      double best_ms = 1e300;
+      for (int w : waves)
+        for (int l : lights) {
+          m4_opts o{};
+          o.tri_wave_max = w;
+          o.c4_light_max = l;
+          uint64_t cnt[6];
+          int rc = m4_count_motifs4_ex(ctx, graph, &o, cnt, nullptr);  // warm
+          if (rc != M4_OK) return rc;
+          if (!have_ref) {
+            memcpy(ref, cnt, sizeof(ref));
+            have_ref = true;
+          } else if (memcmp(ref, cnt, sizeof(ref)) != 0) {
+            return set_error(ctx, M4_EINTERNAL, "autotune: thresholds changed the counts");
+          }
+          double ms = 1e300;
+          for (int r = 0; r < reps; r++) {
+            const double t0 = wall_ms();
+            rc = m4_count_motifs4_ex(ctx, graph, &o, cnt, nullptr);
+            if (rc != M4_OK) return rc;
+            ms = std::min(ms, wall_ms() - t0);
+          }
+          if (ms < best_ms) {
+            best_ms = ms;
+            best.tri_wave_max = w;
+            best.c4_light_max = l;
+          }
+        }
+    }
+    if (batch) {
+      const int64_t G = batch->num_graphs;
+      if (G <= 0) return set_error(ctx, M4_EINVAL, "autotune: empty batch");
+      std::vector<uint64_t> ref((size_t)G * 6), cnt((size_t)G * 6);
+      bool have_ref = false;
+      double best_ms = 1e300;
+      const int lights[] = {32, 64, 128, 256};
+      for (int variant = 0; variant < 2; variant++)
+        for (int l : lights) {
+          ctx->tune.batch_variant = variant;
+          ctx->tune.batch_light = l;
+          m4_opts o{};
+          int rc = count_batch_impl(ctx, batch, &o, cnt.data(), nullptr);  // plan + capture
+          if (rc != M4_OK) {
+            ctx->tune = start;
+            return rc;
+          }
+          if (!have_ref) {
+            ref = cnt;
+            have_ref = true;
+          } else if (ref != cnt) {
+            ctx->tune = start;
+            return set_error(ctx, M4_EINTERNAL, "autotune: thresholds changed the counts");
+          }
+          double ms = 1e300;
+          for (int r = 0; r < reps; r++) {
+            const double t0 = wall_ms();
+            rc = count_batch_impl(ctx, batch, &o, cnt.data(), nullptr);  // replay
+            if (rc != M4_OK) {
+              ctx->tune = start;
+              return rc;
+            }
+            ms = std::min(ms, wall_ms() - t0);
+          }
+          if (ms < best_ms) {
+            best_ms = ms;
+            best.batch_variant = variant;
+            best.batch_light = l;
+          }
+        }
+    }
+  } catch (const HipFail& f) {
+    (void)hipGetLastError();
+    ctx->tune = start;
+    return set_error(ctx, M4_EDEVICE, std::string(f.what) + ": " + hipGetErrorString(f.e));
+  } catch (const Fail& f) {
+    ctx->tune = start;
+    return set_error(ctx, f.code, f.msg);
+  }
+  ctx->tune = best;
+  if (out) to_public(best, out);
+  return M4_OK;
+}

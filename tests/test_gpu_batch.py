@@ -78,3 +78,29 @@ def test_batch_device_arena_and_tunings(ctx):
     for light in (8, 64, 256):
         assert np.array_equal(ctx.count_batch(*dev, c4_light_max=light), ref), light
     assert np.array_equal(ctx.count_batch(*dev, flags=m4.M4_NO_CACHE), ref)
+
+
+def test_autotune_keeps_counts_and_caches(ctx, tmp_path):
+    import paper_2607_12074_amd as m4
+    graphs = [gg.batch_graph(i, seed=8) for i in range(120)]
+    arena = m4.pack_batch(graphs)
+    ref = ctx.count_batch(*arena)
+    g = gg.rmat(12, 8, 0.57, 0.19, 0.19, 4)
+    gref = ctx.count(*g)
+    before = ctx.get_tuning()
+    cache = str(tmp_path / "tune.json")
+    t = ctx.autotune(graph=g, batch=arena, reps=2, cache=cache)
+    assert not t["cached"]
+    assert ctx.get_tuning() == {k: t[k] for k in before}
+    assert np.array_equal(ctx.count_batch(*arena), ref)
+    assert ctx.count(*g) == gref
+    # a second context with the same device and sample sizes reuses the result
+    c2 = m4.Context(0)
+    t2 = c2.autotune(graph=g, batch=arena, cache=cache)
+    assert t2["cached"] and c2.get_tuning() == ctx.get_tuning()
+    for v in (0, 1):
+        c2.set_tuning(batch_variant=v)
+        assert np.array_equal(c2.count_batch(*arena), ref), v
+    c2.close()
+    with pytest.raises(m4.M4Error):
+        ctx.set_tuning(batch_light=0)
