@@ -96,13 +96,15 @@ enum {
   M4_K_C4_WIN32,      /* ... windowed 32-bit LDS counters                      */
   M4_K_C4_HASH,       /* ... LDS hash table                                    */
   M4_K_CLOSURE,       /* closure sums and exact inverse                         */
+  M4_K_TRI_HUBS,      /* hub tables of the long out-lists (triangle probes)     */
   M4_NK = 16
 };
 
 /* Work and timing counters of one call.  basis[] is filled for every call
  * with a non-NULL m4_stats; the k_* counters need M4_STATS and ms_kernel[]
  * needs M4_TIMING.  Per slot:
- *   triangle slots: k_elems = list elements looked up, k_rows = owners,
+ *   triangle slots: k_elems = sum of |N+(v)| over the owners' out-neighbours
+ *                   v (elements a scanning intersection reads), k_rows = owners,
  *                   k_aux = out-list entries of the owners, k_aux2 = sum over
  *                   the triangles (u, v, w), u < v < w, of |N+(w)|
  *   4-cycle slots:  k_elems = wedge endpoints counted, k_rows = owners,
@@ -114,7 +116,8 @@ typedef struct {
   /* non-induced basis: T, K4, C4_ni, S = sum C(d,3), P_ni, Paw_ni, D_ni,
    * sum_e t_e (each < 2^64, else the call returns M4_EOVERFLOW) */
   uint64_t basis[8];
-  uint64_t intersect_steps; /* sorted-list elements looked up (triangle anchors) */
+  uint64_t intersect_steps; /* list elements looked up plus hub-table probes
+                               (triangle anchors)                               */
   uint64_t wedges;          /* 4-cycle wedge endpoints counted                   */
   uint64_t cache_lookups;   /* frontier requests of the 4-clique stage           */
   uint64_t cache_hits;      /* ... served from the signature cache               */
@@ -172,7 +175,12 @@ typedef struct {
                             with 40 KiB (up to 448); default 0                 */
   int32_t batch_light;   /* fused batched kernel: wedge bound of the per-
                             wavefront 4-cycle hash (1..256, default 128)      */
-  int32_t reserved[4];
+  int32_t hub_min;       /* single graph: vertices with out-degree >= this get a
+                            hash table of their out-list, and a triangle owner
+                            probes it for its later out-neighbours instead of
+                            scanning the list when that is cheaper (0 = never,
+                            else 4..65536, default 32)                        */
+  int32_t reserved[3];
 } m4_tuning;
 
 int m4_get_tuning(const m4_ctx* ctx, m4_tuning* out);

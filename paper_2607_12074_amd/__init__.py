@@ -24,7 +24,7 @@ M4_VALIDATE, M4_NO_CACHE, M4_FORCE_PARTITION, M4_STATS, M4_TIMING = 0x1, 0x2, 0x
 M4_PLAIN_LOOP = 0x20
 M4_NK = 16
 KERNELS = ("build", "tri_global", "tri_1024", "tri_512", "tri_256", "tri_128", "tri_wave",
-           "c4_plan", "c4_win16", "c4_win32", "c4_hash", "closure")
+           "c4_plan", "c4_win16", "c4_win32", "c4_hash", "closure", "tri_hubs")
 NAMES = ("star", "path", "paw", "cycle", "diamond", "clique")
 BASIS = ("T", "K4", "C4_ni", "S", "P_ni", "Paw_ni", "D_ni", "sum_t")
 
@@ -77,10 +77,10 @@ class Batch(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("tri_wave_max", ctypes.c_int32), ("c4_light_max", ctypes.c_int32),
                 ("batch_variant", ctypes.c_int32), ("batch_light", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("hub_min", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
     def to_dict(self):
-        return {f: int(getattr(self, f)) for f, _ in self._fields_[:4]}
+        return {f: int(getattr(self, f)) for f, _ in self._fields_[:5]}
 
 
 class Result(ctypes.Structure):

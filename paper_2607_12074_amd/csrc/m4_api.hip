@@ -76,7 +76,8 @@ Prep carve_prep(char* base, int64_t n, int64_t nnz) {
 
 size_t stage_tmp_bytes(int64_t n, int64_t nnz, int64_t dmax, int num_cu) {
   size_t build = build_tmp_bytes(n, nnz);
-  size_t tri = 2 * align256((size_t)n * 4 + 4) + align256(radix_tmp_elems(n, 4) * 8) + 4096;
+  size_t tri = 5 * align256((size_t)n * 4 + 4) + align256(radix_tmp_elems(n, 4) * 8) +
+               align256((size_t)(n + 1) * 8 + 8) + align256(scan_tmp_elems(n) * 8) + 4096;
   (void)dmax;
   (void)num_cu;
   size_t c4 = 2 * align256((size_t)(n + 1) * 8 + 8) + 4 * align256((size_t)n * 4 + 4) +

@@ -218,7 +218,7 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs A) {
     T.flags = A.flags;
     T.cache_rows = A.cache_rows;
     u128_t k4 = 0;
-    unsigned long long st0 = 0, st1 = 0, st2 = 0, st3 = 0, st4 = 0;
+    unsigned long long st0 = 0, st1 = 0, st2 = 0, st3 = 0, st4 = 0, st5 = 0;
     {
       unsigned char* w = U + wid * PW_TRI;
       int32_t* a = reinterpret_cast<int32_t*>(w);
@@ -237,7 +237,7 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs A) {
           continue;
         }
         tri_owner<WAVE, false, true>(T, r, lane, a, sst, soe, slen, spref, colcnt, tag, B, k4,
-                                     st0, st1, st2, st3, st4);
+                                     st0, st1, st2, st3, st4, st5);
       }
     }
     __syncthreads();
@@ -256,7 +256,7 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs A) {
       uint64_t* B =
           reinterpret_cast<uint64_t*>(U + ((7 * 4 * (size_t)(k + 1) + 7) & ~(size_t)7));
       tri_owner<NT, false, false>(T, r, tid, a, sst, soe, slen, spref, colcnt, tag, B, k4, st0,
-                                  st1, st2, st3, st4);
+                                  st1, st2, st3, st4, st5);
       __syncthreads();
     }
     if (tid == 0) s_ndef = 0;

@@ -215,8 +215,10 @@ __global__ __launch_bounds__(H_NT) void k_c4_hash(C4Args A) {
 
 // -------------------------------------------------------- window bucket
 // Segment descriptors of the window owners: for lower neighbour v of owner u
-// the cursor into row v (first entry >= r1), the end of the prefix below u,
-// and the value at the cursor.  Built once per owner by a block of its own.
+// the cursor into row v (first entry >= r1), the end of the stored row and
+// the values at the cursor and 7 entries after it.  The windows stop at the first entry >= their
+// upper end, so the position of u in row v is never needed.  Built once per
+// owner by a block of its own.
 __global__ __launch_bounds__(256) void k_c4_desc(const int32_t* __restrict__ order,
                                                  const int64_t* __restrict__ start,
                                                  const int64_t* __restrict__ seg_off,
@@ -234,11 +236,10 @@ __global__ __launch_bounds__(256) void k_c4_desc(const int32_t* __restrict__ ord
     const int32_t v = ncol[base + i];
     const int64_t rs = nptr[v];
     const int64_t rend = row_len ? rs + row_len[v] : nptr[v + 1];
-    const int64_t e = lower_index(ncol, rs + dlo[v], rend, u);  // position of u
     // first entry >= r1: precomputed for full rows, searched for stored prefixes
-    int64_t c = lowcut ? rs + lowcut[v] : lower_index(ncol, rs, e, (int32_t)r1);
-    if (c > e) c = e;
-    desc[so + i] = make_int4((int)c, (int)e, c < e ? ncol[c] : INT_MAX, 0);
+    int64_t c = lowcut ? rs + lowcut[v] : lower_index(ncol, rs, rend, (int32_t)r1);
+    desc[so + i] = make_int4((int)c, (int)rend, c < rend ? ncol[c] : INT_MAX,
+                             c + 7 < rend ? ncol[c + 7] : INT_MAX);
   }
 }
 
@@ -259,26 +260,48 @@ __global__ void k_c4_heavy_len(const int32_t* __restrict__ order, const int64_t*
   if (h < H) len[h] = dlo[order[b + h]];
 }
 
-constexpr int W_NT = 1024, W_GL = 8, W_NG = W_NT / W_GL, W_NCH = 8;
+constexpr int W_NT = 1024, W_GL = 8, W_NG = W_NT / W_GL, W_NCH = 8, W_SHORT = 8;
+constexpr int W_BATCH = 4096;  // segments per pass (bounds the long-visit queue)
 
-// One heavy owner per workgroup, windows in order.  Each 8-lane group walks
-// its share of the owner's segments; while it counts one segment the loads
-// of the next segment's first 64 entries and the descriptor after that are
-// already in flight.  A segment whose next value lies beyond the window
-// costs only its descriptor.
+// One counter update of the window: adds the old value to the running sum
+// of C(c, 2) (every increment of c_u[w] from c to c+1 adds c).
+template <bool NARROW>
+__device__ __forceinline__ uint32_t window_add(uint32_t* cnt, uint32_t o) {
+  if (NARROW) {
+    const uint32_t sh = (o & 1u) << 4;
+    const uint32_t old = atomicAdd(&cnt[o >> 1], 1u << sh);
+    return (old >> sh) & 0xffffu;
+  }
+  return atomicAdd(&cnt[o], 1u);
+}
+
+__device__ __forceinline__ int32_t row_at(const int32_t* ncol, int64_t i, int64_t e) {
+  return i < e ? ncol[i] : INT_MAX;
+}
+
+// One heavy owner per workgroup, windows of counters in LDS in order.  A
+// segment is one lower neighbour's row; its descriptor holds the cursor (the
+// first entry not yet counted), the row end, and the values at the cursor and
+// 7 entries after it, so the length of its visit to a window is known to be
+// 0, at most 8, or more without reading the row.  Per pass over W_BATCH
+// segments, every thread first takes whole segments by itself: empty visits
+// cost the descriptor only, short visits (<= 8 entries, most of them) one
+// thread with 8 independent loads; longer visits are queued in LDS and then
+// walked by 8-lane groups, 64 entries per step with the next step's loads in
+// flight.
 template <bool NARROW>
 __global__ __launch_bounds__(W_NT) void k_c4_window(C4Args A) {
   constexpr int WIN = NARROW ? C4_WIN16 : C4_WIN32;
   constexpr int WORDS = NARROW ? WIN / 2 : WIN;
   __shared__ uint32_t cnt[WORDS];
-  __shared__ int s_item;
+  __shared__ int32_t queue[W_BATCH];
+  __shared__ int s_item, s_q;
   const int tid = threadIdx.x, lane = tid & (WAVE - 1);
   const int g = tid / W_GL, gl = tid & (W_GL - 1);
   const int gshift = lane & ~(W_GL - 1);
   const uint64_t gmask = (1ull << W_GL) - 1;
   const int64_t b0 = A.start[A.bucket], cnt_items = A.start[A.bucket + 1] - b0;
   const int64_t hbase = b0 - A.start[CB_WIN16];
-  const int4 kEmpty = make_int4(0, 0, INT_MAX, 0);
   u128_t acc = 0;
   unsigned long long wedges = 0, owners = 0, segs = 0, visits = 0;
   for (;;) {
@@ -301,27 +324,60 @@ __global__ __launch_bounds__(W_NT) void k_c4_window(C4Args A) {
     for (int64_t lo = A.r1; lo < u; lo += WIN) {
       const int32_t hi = (int32_t)(lo + WIN < u ? lo + WIN : u);
       for (int i = tid; i < WORDS; i += W_NT) cnt[i] = 0;
-      __syncthreads();
-      int sg = g;
-      int4 dA = sg < nl ? D[sg] : kEmpty;
-      int4 dB = sg + W_NG < nl ? D[sg + W_NG] : kEmpty;
-      int32_t wa[W_NCH];
+      for (int s0 = 0; s0 < nl; s0 += W_BATCH) {
+        const int s1 = s0 + W_BATCH < nl ? s0 + W_BATCH : nl;
+        if (tid == 0) s_q = 0;
+        __syncthreads();
+        // ---- whole segments per thread
+        for (int sg = s0 + tid; sg < s1; sg += W_NT) {
+          const int4 d = D[sg];
+          if (d.z >= hi) continue;  // nothing in this window
+          if (d.w < hi) {           // more than 8 entries: queue it
+            queue[atomicAdd(&s_q, 1)] = sg;
+            continue;
+          }
+          const int64_t c = d.x, e = d.y;
+          int32_t x[W_SHORT];
 #pragma unroll
-      for (int k2 = 0; k2 < W_NCH; k2++) {
-        const int32_t idx = dA.x + gl + W_GL * k2;
-        wa[k2] = (dA.z < hi && idx < dA.y) ? A.ncol[idx] : INT_MAX;
-      }
-      while (sg < nl) {
-        const int s2 = sg + 2 * W_NG;
-        const int4 dC = s2 < nl ? D[s2] : kEmpty;
-        int32_t wb[W_NCH];
+          for (int j = 0; j < W_SHORT; j++) x[j] = row_at(A.ncol, c + j, e);
+          int took = 0;
+#pragma unroll
+          for (int j = 0; j < W_SHORT; j++)
+            if (x[j] < hi) {
+              acc += window_add<NARROW>(cnt, (uint32_t)(x[j] - (int32_t)lo));
+              took++;
+            }
+          wedges += (unsigned long long)took;
+          // x[took] >= hi exists because the entry 7 after the cursor is >= hi
+          int32_t znext = x[0];
+#pragma unroll
+          for (int j = 1; j < W_SHORT; j++)
+            if (j == took) znext = x[j];
+          D[sg] = make_int4((int)(c + took), (int)e, znext, row_at(A.ncol, c + took + 7, e));
+        }
+        __syncthreads();
+        // ---- queued long segments, one 8-lane group each
+        const int nq = s_q;
+        int qi = g;
+        int4 dA = qi < nq ? D[queue[qi]] : make_int4(0, 0, INT_MAX, INT_MAX);
+        int32_t wa[W_NCH];
 #pragma unroll
         for (int k2 = 0; k2 < W_NCH; k2++) {
-          const int32_t idx = dB.x + gl + W_GL * k2;
-          wb[k2] = (dB.z < hi && idx < dB.y) ? A.ncol[idx] : INT_MAX;
+          const int64_t idx = (int64_t)dA.x + gl + W_GL * k2;
+          wa[k2] = qi < nq ? row_at(A.ncol, idx, dA.y) : INT_MAX;
         }
-        if (dA.z < hi) {  // uniform in the group
-          int32_t c = dA.x, vnext = INT_MAX;
+        while (qi < nq) {  // uniform in the group
+          const int sg = queue[qi];
+          const int qn = qi + W_NG;
+          const int4 dB = qn < nq ? D[queue[qn]] : make_int4(0, 0, INT_MAX, INT_MAX);
+          int32_t wb[W_NCH];
+#pragma unroll
+          for (int k2 = 0; k2 < W_NCH; k2++) {
+            const int64_t idx = (int64_t)dB.x + gl + W_GL * k2;
+            wb[k2] = qn < nq ? row_at(A.ncol, idx, dB.y) : INT_MAX;
+          }
+          int64_t c = dA.x;
+          int32_t vnext = INT_MAX;
           for (;;) {
             int tot = 0;
             bool stop = false;
@@ -330,14 +386,7 @@ __global__ __launch_bounds__(W_NT) void k_c4_window(C4Args A) {
               if (!stop) {
                 const bool in = wa[k2] < hi;
                 if (in) {
-                  const uint32_t o = (uint32_t)(wa[k2] - (int32_t)lo);
-                  if (NARROW) {
-                    const uint32_t sh = (o & 1u) << 4;
-                    const uint32_t old = atomicAdd(&cnt[o >> 1], 1u << sh);
-                    acc += (old >> sh) & 0xffffu;
-                  } else {
-                    acc += atomicAdd(&cnt[o], 1u);
-                  }
+                  acc += window_add<NARROW>(cnt, (uint32_t)(wa[k2] - (int32_t)lo));
                   wedges++;
                 }
                 // rows are sorted: the entries inside the window are a prefix
@@ -352,20 +401,16 @@ __global__ __launch_bounds__(W_NT) void k_c4_window(C4Args A) {
             c += tot;
             if (stop) break;
 #pragma unroll
-            for (int k2 = 0; k2 < W_NCH; k2++) {
-              const int32_t idx = c + gl + W_GL * k2;
-              wa[k2] = idx < dA.y ? A.ncol[idx] : INT_MAX;
-            }
+            for (int k2 = 0; k2 < W_NCH; k2++) wa[k2] = row_at(A.ncol, c + gl + W_GL * k2, dA.y);
           }
-          if (gl == 0) D[sg] = make_int4(c, dA.y, vnext, 0);
-        }
-        sg += W_NG;
-        dA = dB;
-        dB = dC;
+          if (gl == 0) D[sg] = make_int4((int)c, dA.y, vnext, row_at(A.ncol, c + 7, dA.y));
+          qi = qn;
+          dA = dB;
 #pragma unroll
-        for (int k2 = 0; k2 < W_NCH; k2++) wa[k2] = wb[k2];
+          for (int k2 = 0; k2 < W_NCH; k2++) wa[k2] = wb[k2];
+        }
+        __syncthreads();
       }
-      __syncthreads();
     }
   }
   block_add_u128<W_NT>(&A.scal->acc[ACC_C4], acc);

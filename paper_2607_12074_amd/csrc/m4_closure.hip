@@ -21,8 +21,10 @@ namespace m4 {
 
 namespace {
 
-constexpr int CL_NT = 256;
+constexpr int CL_NT = 256, CL_G = 8;
 
+// CL_G lanes per vertex: the out-list, its heads' degrees and its t_e are
+// read by consecutive lanes, several vertices per wavefront.
 __global__ __launch_bounds__(CL_NT) void k_closure(const int64_t* __restrict__ nptr,
                                                    const int32_t* __restrict__ dlo,
                                                    const int32_t* __restrict__ dplus,
@@ -32,20 +34,23 @@ __global__ __launch_bounds__(CL_NT) void k_closure(const int64_t* __restrict__ n
                                                    const uint32_t* __restrict__ t, int64_t lo,
                                                    int64_t hi, Scal* scal) {
   u128_t S = 0, P = 0, D = 0, Paw2 = 0, St = 0;
-  for (int64_t u = lo + (int64_t)blockIdx.x * CL_NT + threadIdx.x; u < hi;
-       u += (int64_t)gridDim.x * CL_NT) {
+  const int gl = threadIdx.x & (CL_G - 1);
+  const int64_t groups = (int64_t)gridDim.x * (CL_NT / CL_G);
+  for (int64_t u = lo + ((int64_t)blockIdx.x * CL_NT + threadIdx.x) / CL_G; u < hi; u += groups) {
     const uint64_t du = (uint32_t)dr[u];
-    if (du >= 3) S += (u128_t)du * (du - 1) * (du - 2) / 6;
+    if (gl == 0 && du >= 3) S += (u128_t)du * (du - 1) * (du - 2) / 6;
     const int k = dplus[u];
     const int64_t rb = nptr[u] + dlo[u], oe = optr[u];
-    for (int j = 0; j < k; j++) {
+    uint64_t st = 0;  // sum of t_e over this lane's edges of u: < 2^31 * 2^32
+    for (int j = gl; j < k; j += CL_G) {
       const uint64_t dv = (uint32_t)dr[ncol[rb + j]];
       const uint64_t te = t[oe + j];
       P += (u128_t)((du - 1) * (dv - 1));  // each product < 2^62
-      St += te;
-      D += (u128_t)(te * (te - 1) / 2);
-      if (te) Paw2 += (u128_t)(te * (du + dv - 4));
+      st += te;
+      D += (u128_t)(te * (te - 1) / 2);     // te < 2^32: < 2^63 per edge
+      if (te) Paw2 += (u128_t)te * (du + dv - 4);
     }
+    St += st;
   }
   block_add_u128<CL_NT>(&scal->acc[ACC_S], S);
   block_add_u128<CL_NT>(&scal->acc[ACC_P], P);
@@ -70,7 +75,7 @@ void closure_run(const Prep& P, Scal* scal, uint32_t flags, hipStream_t s) {
   (void)flags;
   const int64_t lo = P.own_lo, hi = P.hi();
   if (hi <= lo) return;
-  int64_t blocks = ceil_div(hi - lo, CL_NT);
+  int64_t blocks = ceil_div((hi - lo) * CL_G, CL_NT);
   if (blocks > 4096) blocks = 4096;
   k_closure<<<(unsigned)blocks, CL_NT, 0, s>>>(P.nptr, P.dlo, P.dplus, P.optr, P.ncol, P.dr, P.t,
                                                lo, hi, scal);

@@ -43,6 +43,8 @@ struct Scal {
   unsigned int dmax;
   int err;
   unsigned int work[8];
+  unsigned int nhub;  // vertices with a hub table (triangle stage)
+  unsigned int pad2;
   int64_t tri_start[TB_N + 1];
   int64_t c4_start[CB_N + 1];
   unsigned long long out[6];
@@ -98,6 +100,7 @@ struct Tuning {
   int grid_mult = 8;        // persistent blocks per CU for light kernels
   int batch_variant = 0;    // batched kernel: 0 = 1024 threads / 96 KiB, 1 = 512 / 40 KiB
   int batch_light = 128;    // batched kernel: wedge bound of the wavefront hash
+  int hub_min = 32;         // out-degree from which a vertex gets a hub table (0: none)
 };
 
 // Optional per-launch HIP event pairs (M4_TIMING).

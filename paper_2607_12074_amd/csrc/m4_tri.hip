@@ -37,7 +37,8 @@ __global__ __launch_bounds__(NT) void k_tri_lds(TriArgs A) {
   __shared__ int s_item;
   const int64_t b0 = A.start[A.bucket], cnt = A.start[A.bucket + 1] - b0;
   u128_t k4 = 0;
-  unsigned long long steps = 0, looks = 0, hits = 0, ksum = 0, wstream = 0, owners = 0;
+  unsigned long long steps = 0, looks = 0, hits = 0, ksum = 0, wstream = 0, owners = 0,
+                     escan = 0;
   for (;;) {
     if (threadIdx.x == 0) s_item = (int)atomicAdd(A.work, (unsigned)A.grab);
     __syncthreads();
@@ -46,9 +47,9 @@ __global__ __launch_bounds__(NT) void k_tri_lds(TriArgs A) {
     if (first >= cnt) break;
     const int64_t last = first + A.grab < cnt ? first + A.grab : cnt;
     for (int64_t item = first; item < last; item++) {
-      tri_owner<NT, false, false, HASH>(A, A.order[b0 + item], threadIdx.x, a, sst, soe, slen,
-                                        spref, colcnt, tag, B, k4, steps, looks, hits, ksum,
-                                        wstream, hk, hv);
+      tri_owner<NT, false, false, HASH, true>(A, A.order[b0 + item], threadIdx.x, a, sst, soe,
+                                              slen, spref, colcnt, tag, B, k4, steps, looks,
+                                              hits, ksum, wstream, escan, hk, hv);
       owners++;
     }
   }
@@ -57,7 +58,7 @@ __global__ __launch_bounds__(NT) void k_tri_lds(TriArgs A) {
     block_add_u64<NT>(&A.scal->stat[ST_STEPS], steps);
     block_add_u64<NT>(&A.scal->stat[ST_LOOKUPS], looks);
     block_add_u64<NT>(&A.scal->stat[ST_HITS], hits);
-    block_add_u64<NT>(&A.scal->kstat[A.slot][0], steps);
+    block_add_u64<NT>(&A.scal->kstat[A.slot][0], escan);
     block_add_u64<NT>(&A.scal->kstat[A.slot][1], threadIdx.x == 0 ? owners : 0);
     block_add_u64<NT>(&A.scal->kstat[A.slot][2], ksum);
     block_add_u64<NT>(&A.scal->kstat[A.slot][3], wstream);
@@ -78,15 +79,17 @@ __global__ __launch_bounds__(NT) void k_tri_global(TriArgs A) {
   uint32_t* colcnt = (uint32_t*)(base + 5 * K + 1);
   uint32_t* tag = (uint32_t*)(base + 6 * K + 1);
   u128_t k4 = 0;
-  unsigned long long steps = 0, looks = 0, hits = 0, ksum = 0, wstream = 0, owners = 0;
+  unsigned long long steps = 0, looks = 0, hits = 0, ksum = 0, wstream = 0, owners = 0,
+                     escan = 0;
   for (;;) {
     if (threadIdx.x == 0) s_item = (int)atomicAdd(A.work, 1u);
     __syncthreads();
     const int64_t item = s_item;
     __syncthreads();
     if (item >= cnt) break;
-    tri_owner<NT, true>(A, A.order[b0 + item], threadIdx.x, a, sst, soe, slen, spref, colcnt, tag, B, k4,
-                        steps, looks, hits, ksum, wstream);
+    tri_owner<NT, true, false, false, true>(A, A.order[b0 + item], threadIdx.x, a, sst, soe, slen,
+                                            spref, colcnt, tag, B, k4, steps, looks, hits, ksum,
+                                            wstream, escan);
     owners++;
     __threadfence();
   }
@@ -95,7 +98,7 @@ __global__ __launch_bounds__(NT) void k_tri_global(TriArgs A) {
     block_add_u64<NT>(&A.scal->stat[ST_STEPS], steps);
     block_add_u64<NT>(&A.scal->stat[ST_LOOKUPS], looks);
     block_add_u64<NT>(&A.scal->stat[ST_HITS], hits);
-    block_add_u64<NT>(&A.scal->kstat[A.slot][0], steps);
+    block_add_u64<NT>(&A.scal->kstat[A.slot][0], escan);
     block_add_u64<NT>(&A.scal->kstat[A.slot][1], threadIdx.x == 0 ? owners : 0);
     block_add_u64<NT>(&A.scal->kstat[A.slot][2], ksum);
     block_add_u64<NT>(&A.scal->kstat[A.slot][3], wstream);
@@ -122,6 +125,56 @@ __global__ void k_tri_keys(const int32_t* __restrict__ dplus, int64_t n, int64_t
     atomicMax((unsigned int*)&scal->work[7], (unsigned int)k);
   }
   key[u] = b;
+}
+
+// Hub tables (a vertex with out-degree >= hub_min gets an open-addressing
+// table of its out-list, mapping a rank to its position in N+(v)).
+__global__ void k_hub_size(const int32_t* __restrict__ dplus, int64_t n, int hub_min,
+                           int32_t* __restrict__ hsz, int32_t* __restrict__ hubs,
+                           unsigned int* __restrict__ nhub) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int L = dplus[v];
+  const bool hub = L >= hub_min;
+  hsz[v] = hub ? (1 << hub_bits(L)) : 0;
+  if (hub) hubs[atomicAdd(nhub, 1u)] = (int32_t)v;
+}
+
+__global__ void k_hub_off(const int32_t* __restrict__ hsz, const int64_t* __restrict__ off64,
+                          int64_t n, int32_t* __restrict__ hoff) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  hoff[v] = hsz[v] ? (int32_t)off64[v] : -1;
+}
+
+// one wavefront per hub (grid-stride over the hub list); lanes insert the
+// out-list entries with 64-bit compare-and-swap
+__global__ __launch_bounds__(256) void k_hub_insert(const int32_t* __restrict__ dplus,
+                                                    const int64_t* __restrict__ nptr,
+                                                    const int32_t* __restrict__ dlo,
+                                                    const int32_t* __restrict__ ncol,
+                                                    const int32_t* __restrict__ hoff,
+                                                    const int32_t* __restrict__ hubs,
+                                                    const unsigned int* __restrict__ nhub,
+                                                    unsigned long long* __restrict__ htab) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int64_t nw = (int64_t)gridDim.x * (blockDim.x / WAVE);
+  const int64_t nh = *nhub;
+  for (int64_t hix = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE; hix < nh;
+       hix += nw) {
+    const int32_t v = hubs[hix];
+    const int32_t off = hoff[v];
+    const int L = dplus[v];
+    const int bits = hub_bits(L);
+    const uint32_t mask = (1u << bits) - 1u;
+    const int64_t st = nptr[v] + dlo[v];
+    for (int j = lane; j < L; j += WAVE) {
+      const int32_t x = ncol[st + j];
+      uint32_t h = hub_hash(x, bits);
+      const unsigned long long e = ((unsigned long long)(uint32_t)x << 32) | (uint32_t)j;
+      while (atomicCAS(&htab[(int64_t)off + h], HUB_EMPTY, e) != HUB_EMPTY) h = (h + 1) & mask;
+    }
+  }
 }
 
 }  // namespace
@@ -153,12 +206,54 @@ void tri_run(const Prep& P, Scal* scal, const Tuning& tu, uint32_t flags, uint32
   k_tri_keys<<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(P.dplus, n, P.own_lo, P.hi(), wave_max,
                                                          key, scal);
   radix_pass(key, nullptr, n, 0, 4, nullptr, order, rtmp, start, s);
+  // hub tables: resident runs only (a partition holds only its halo rows)
+  const bool hubs = tu.hub_min > 0 && P.own_hi < 0 && !P.row_len;
+  int32_t* hsz = nullptr;
+  int32_t* hoff = nullptr;
+  int32_t* hub_list = nullptr;
+  int64_t* hoff64 = nullptr;
+  if (hubs) {
+    hsz = tmp.take<int32_t>(n);
+    hoff = tmp.take<int32_t>(n);
+    hub_list = tmp.take<int32_t>(n);
+    hoff64 = tmp.take<int64_t>(n + 1);
+    int64_t* hst = tmp.take<int64_t>(scan_tmp_elems(n));
+    if (!hsz || !hoff || !hub_list || !hoff64 || !hst)
+      throw Fail(M4_EINTERNAL, "workspace too small (hubs)");
+    fill_u32(&scal->nhub, 0, 1, s);
+    k_hub_size<<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(P.dplus, n, tu.hub_min, hsz, hub_list,
+                                                          &scal->nhub);
+    scan_i32(hsz, n, hoff64, hst, s);
+  }
   // largest out-degree of the global bucket decides its scratch size
   unsigned int kmax_g = 0;
   int64_t hstart[17];
+  int64_t hub_slots = 0;
   M4_HIP(hipMemcpyAsync(&kmax_g, &scal->work[7], sizeof(kmax_g), hipMemcpyDeviceToHost, s));
   M4_HIP(hipMemcpyAsync(hstart, start, sizeof(hstart), hipMemcpyDeviceToHost, s));
+  if (hubs) M4_HIP(hipMemcpyAsync(&hub_slots, hoff64 + n, 8, hipMemcpyDeviceToHost, s));
   M4_HIP(hipStreamSynchronize(s));
+  // scratch: hub tables, then the dense-owner bitmaps
+  size_t hub_bytes = 0, dense_bytes = 0, dense_bits = 0, dense_blocks = 0;
+  const bool use_hubs = hubs && hub_slots > 0 && hub_slots < (int64_t(1) << 31);
+  if (use_hubs) hub_bytes = ((size_t)hub_slots * 8 + 255) & ~size_t(255);
+  if (kmax_g > 0) {
+    size_t K = kmax_g, WK = (K + 63) / 64;
+    size_t per_block = K * WK * 8 + (7 * K + 2) * 4;
+    int64_t owners = hstart[TK_GLOBAL + 1] - hstart[TK_GLOBAL];
+    int64_t blocks = (int64_t)((size_t(1) << 30) / per_block);
+    if (blocks > 64) blocks = 64;
+    if (blocks > owners) blocks = owners;
+    if (blocks < 1) blocks = 1;
+    dense_blocks = (size_t)blocks;
+    dense_bits = ((size_t)blocks * K * WK * 8 + 255) & ~size_t(255);
+    dense_bytes = dense_bits + (size_t)blocks * (7 * K + 2) * 4;
+  }
+  char* scratch = nullptr;
+  if (hub_bytes + dense_bytes > 0) {
+    scratch = big_scratch(hub_bytes + dense_bytes);
+    if (!scratch) throw Fail(M4_ENOMEM, "scratch for hub tables and dense out-lists does not fit");
+  }
 
   TriArgs A{};
   A.order = order;
@@ -172,6 +267,18 @@ void tri_run(const Prep& P, Scal* scal, const Tuning& tu, uint32_t flags, uint32
   A.scal = scal;
   A.flags = flags;
   A.cache_rows = cache_rows;
+  if (use_hubs) {
+    if (kt) kt->begin(M4_K_TRI_HUBS, s);
+    unsigned long long* htab = reinterpret_cast<unsigned long long*>(scratch);
+    k_hub_off<<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(hsz, hoff64, n, hoff);
+    fill_u32(htab, 0xffffffffu, (size_t)hub_slots * 2, s);
+    k_hub_insert<<<(unsigned)(num_cu * 8), 256, 0, s>>>(P.dplus, P.nptr, P.dlo, P.ncol, hoff,
+                                                         hub_list, &scal->nhub, htab);
+    A.hoff = hoff;
+    A.htab = htab;
+    A.hub_min = tu.hub_min;
+    if (kt) kt->end(M4_K_TRI_HUBS, s);
+  }
 
   auto run_lds = [&](auto kmax_tag, auto nt_tag, int bucket, int slot, int blocks_per_cu) {
     constexpr int KM = decltype(kmax_tag)::value;
@@ -189,18 +296,10 @@ void tri_run(const Prep& P, Scal* scal, const Tuning& tu, uint32_t flags, uint32
   };
   // heaviest buckets first so that their tails overlap the light ones
   if (kmax_g > 0) {
-    size_t K = kmax_g, WK = (K + 63) / 64;
-    size_t per_block = K * WK * 8 + (7 * K + 2) * 4;
-    int64_t owners = hstart[TK_GLOBAL + 1] - hstart[TK_GLOBAL];
-    int64_t blocks = (int64_t)((size_t(1) << 30) / per_block);
-    if (blocks > 64) blocks = 64;
-    if (blocks > owners) blocks = owners;
-    if (blocks < 1) blocks = 1;
-    size_t bits_bytes = ((size_t)blocks * K * WK * 8 + 255) & ~size_t(255);
-    char* big = big_scratch(bits_bytes + (size_t)blocks * (7 * K + 2) * 4);
-    if (!big) throw Fail(M4_ENOMEM, "scratch for dense out-lists does not fit");
-    uint64_t* gbits = reinterpret_cast<uint64_t*>(big);
-    int32_t* garr = reinterpret_cast<int32_t*>(big + bits_bytes);
+    size_t K = kmax_g;
+    uint64_t* gbits = reinterpret_cast<uint64_t*>(scratch + hub_bytes);
+    int32_t* garr = reinterpret_cast<int32_t*>(scratch + hub_bytes + dense_bits);
+    const int64_t blocks = (int64_t)dense_blocks;
     A.bucket = TK_GLOBAL;
     A.slot = M4_K_TRI_GLOBAL;
     A.grab = 1;

@@ -39,7 +39,22 @@ struct TriArgs {
   int kmax;
   uint64_t* gbits;
   int32_t* garr;
+  // hub tables: open-addressing tables of the out-lists of vertices with
+  // out-degree >= hub_min (entry = key << 32 | position, empty = ~0)
+  const int32_t* hoff;    // table offset per vertex, -1 without a table
+  const unsigned long long* htab;
+  int hub_min;            // 0: no tables
 };
+
+constexpr unsigned long long HUB_EMPTY = ~0ull;
+
+// log2 of the slots of the table of a vertex with out-degree L >= 1: the
+// power of two >= 2L (load factor <= 1/2).
+__host__ __device__ __forceinline__ int hub_bits(int L) { return 32 - __builtin_clz(2u * L - 1u); }
+
+__device__ __forceinline__ uint32_t hub_hash(int32_t x, int bits) {
+  return ((uint32_t)x * 0x9E3779B1u) >> (32 - bits);
+}
 
 template <typename T>
 __device__ __forceinline__ T ld(const T* p, bool fresh) {
@@ -72,10 +87,17 @@ __device__ __forceinline__ uint64_t k4_recompute(const int32_t* ncol, const int3
 // (LDS or global) and bitmap rows of W words each in `B`.
 // HASH: positions of the out-list are found through an LDS hash table
 // (hk/hv, 2H >= 2k slots) instead of a binary search over a[].
-// Work counters: steps (out-list elements looked up), looks/hits (frontier
-// cache), ksum (out-list entries of the owner), wstream (sum over the
-// triangles (u, v, w) of |N+(w)|, the list a merge-based 4-clique step reads).
-template <int NT, bool FRESH, bool WAVE_ONLY = false, bool HASH = false>
+// PROBE: a row i whose head v = a[i] has a hub table is resolved by probing
+// that table for the later entries a[i+1..k) when that is cheaper than
+// scanning N+(v) (k-1-i probes at about 4/3 reads each against |N+(v)|
+// reads); the table returns the position of the hit in N+(v), which indexes
+// the far edge's triangle count.  Both ways find the same triangles.
+// Work counters: steps (elements looked up or probed), looks/hits (frontier
+// cache), ksum (out-list entries of the owner), escan (sum of |N+(v)| over the
+// owner's out-neighbours v, the elements a scanning intersection reads),
+// wstream (sum over the triangles (u, v, w) of |N+(w)|, the list a
+// merge-based 4-clique step reads).
+template <int NT, bool FRESH, bool WAVE_ONLY = false, bool HASH = false, bool PROBE = false>
 __device__ __forceinline__ void tri_owner(const TriArgs& A, int32_t u, const int tid, int32_t* a,
                                           int32_t* sst,
                                           int32_t* soe, int32_t* slen, int32_t* spref,
@@ -83,7 +105,8 @@ __device__ __forceinline__ void tri_owner(const TriArgs& A, int32_t u, const int
                                           u128_t& k4acc,
                                           unsigned long long& steps, unsigned long long& looks,
                                           unsigned long long& hits, unsigned long long& ksum,
-                                          unsigned long long& wstream, int32_t* hk = nullptr,
+                                          unsigned long long& wstream,
+                                          unsigned long long& escan, int32_t* hk = nullptr,
                                           int16_t* hv = nullptr) {
   const int k = A.dplus[u];
   const int64_t rb = A.nptr[u] + A.dlo[u];
@@ -93,9 +116,15 @@ __device__ __forceinline__ void tri_owner(const TriArgs& A, int32_t u, const int
   for (int i = tid; i < k; i += NT) {
     int32_t v = A.ncol[rb + i];
     a[i] = v;
-    sst[i] = (int32_t)(A.nptr[v] + A.dlo[v]);
+    const int L = A.dplus[v];
+    int32_t st = (int32_t)(A.nptr[v] + A.dlo[v]);
+    if (PROBE && A.hub_min > 0 && L >= A.hub_min && 4 * (k - 1 - i) < 3 * L) {
+      const int32_t off = A.hoff[v];
+      if (off >= 0) st = -1 - off;  // probe row: table offset, negated
+    }
+    sst[i] = st;
     soe[i] = (int32_t)A.optr[v];
-    slen[i] = A.dplus[v];
+    slen[i] = L;
     colcnt[i] = 0;
   }
   for (int i = tid; i < k * W; i += NT) B[i] = 0;
@@ -116,29 +145,35 @@ __device__ __forceinline__ void tri_owner(const TriArgs& A, int32_t u, const int
       hv[h] = (int16_t)i;
     }
   }
-  // exclusive prefix of the out-degrees of a[0..k) into spref[0..k]
+  // exclusive prefix of the row work of a[0..k) into spref[0..k]: |N+(a[i])|
+  // elements for a scanned row, k-1-i probes for a probed row
   {
     const int per = (k + NT - 1) / NT;
     const int lo = tid * per;
     int64_t s = 0;
-    for (int i = lo; i < lo + per && i < k; i++) s += slen[i];
+    for (int i = lo; i < lo + per && i < k; i++) {
+      s += (PROBE && sst[i] < 0) ? (k - 1 - i) : slen[i];
+      escan += (unsigned long long)slen[i];
+    }
     int64_t tot;
     int64_t run = block_excl_scan64<NT>(s, &tot);
     for (int i = lo; i < lo + per && i < k; i++) {
       spref[i] = (int32_t)run;
-      run += slen[i];
+      run += (PROBE && sst[i] < 0) ? (k - 1 - i) : slen[i];
     }
     if (tid == 0) spref[k] = (int32_t)tot;
   }
   TRI_SYNC();
   const int total = spref[k];
   // Flattened (row, element) pairs: thread tid takes q = tid, tid + NT, ...;
-  // the row index only moves forward, and four element loads are issued
-  // before the four lookups so that their latencies overlap.
+  // the row index only moves forward, and four element loads (or first
+  // probes) are issued before the four lookups so that their latencies
+  // overlap.
   int i = tid < total ? upper_index(spref, k, tid) : 0;
   int ii[4], jj[4];
   int32_t xx[4];
-  // loads of the next batch are issued before the lookups of the current one
+  uint32_t hh[4];
+  unsigned long long ee[4];
   auto fetch = [&](int q0) {
 #pragma unroll
     for (int r = 0; r < 4; r++) {
@@ -148,7 +183,16 @@ __device__ __forceinline__ void tri_owner(const TriArgs& A, int32_t u, const int
         while (spref[i + 1] <= q) i++;
         ii[r] = i;
         jj[r] = q - spref[i];
-        xx[r] = A.ncol[sst[i] + jj[r]];
+        const int32_t st = sst[i];
+        if (PROBE && st < 0) {
+          const int32_t x = a[i + 1 + jj[r]];
+          const uint32_t h = hub_hash(x, hub_bits(slen[i]));
+          xx[r] = x;
+          hh[r] = h;
+          ee[r] = A.htab[(int64_t)(-1 - st) + h];
+        } else {
+          xx[r] = A.ncol[st + jj[r]];
+        }
       }
     }
   };
@@ -156,11 +200,15 @@ __device__ __forceinline__ void tri_owner(const TriArgs& A, int32_t u, const int
   for (int q0 = tid; q0 < total; q0 += 4 * NT) {
     int ci[4], cj[4];
     int32_t cx[4];
+    uint32_t ch[4];
+    unsigned long long ce[4];
 #pragma unroll
     for (int r = 0; r < 4; r++) {
       ci[r] = ii[r];
       cj[r] = jj[r];
       cx[r] = xx[r];
+      ch[r] = hh[r];
+      ce[r] = ee[r];
     }
     if (q0 + 4 * NT < total) fetch(q0 + 4 * NT);
 #pragma unroll
@@ -168,9 +216,27 @@ __device__ __forceinline__ void tri_owner(const TriArgs& A, int32_t u, const int
       if (ci[r] < 0) continue;
       const int ir = ci[r];
       const int32_t x = cx[r];
-      int p;
-      if (HASH) {
+      int p, pos;
+      if (PROBE && sst[ir] < 0) {
+        // x = a[p] looked up in the table of a[ir]
+        p = ir + 1 + cj[r];
+        const int64_t off = -1 - (int64_t)sst[ir];
+        const uint32_t mask = (1u << hub_bits(slen[ir])) - 1u;
+        uint32_t h = ch[r];
+        unsigned long long e = ce[r];
+        pos = -1;
+        while (e != HUB_EMPTY) {
+          if ((int32_t)(e >> 32) == x) {
+            pos = (int)(uint32_t)e;
+            break;
+          }
+          h = (h + 1) & mask;
+          e = A.htab[off + h];
+        }
+        if (pos < 0) p = -1;
+      } else if (HASH) {
         // x > a[ir], so a hit is always a position after ir
+        pos = cj[r];
         uint32_t h = ((uint32_t)x * 0x9E3779B1u) >> hshift;
         p = -1;
         for (;;) {
@@ -183,6 +249,7 @@ __device__ __forceinline__ void tri_owner(const TriArgs& A, int32_t u, const int
           h = (h + 1) & (uint32_t)(H - 1);
         }
       } else {
+        pos = cj[r];
         p = (int)lower_index(a, (int64_t)ir + 1, (int64_t)k, x);
         if (p >= k || a[p] != x) p = -1;
       }
@@ -190,7 +257,7 @@ __device__ __forceinline__ void tri_owner(const TriArgs& A, int32_t u, const int
       if (p >= 0) {
         atomicOr((unsigned long long*)&B[ir * W + (p >> 6)], 1ull << (p & 63));
         atomicAdd(&colcnt[p], 1u);
-        atomicAdd(&A.t[soe[ir] + cj[r]], 1u);
+        atomicAdd(&A.t[soe[ir] + pos], 1u);
       }
     }
   }
@@ -228,7 +295,10 @@ __device__ __forceinline__ void tri_owner(const TriArgs& A, int32_t u, const int
             c += __popcll(ld(&B[i * W + ww], FRESH) & ld(&B[p * W + ww], FRESH));
           k4acc += c;
         } else {
-          k4acc += k4_recompute(A.ncol, a, k, p, sst[i], slen[i], sst[p], slen[p]);
+          // probed rows keep a table offset in sst[]: take the list start again
+          const int64_t si = (PROBE && sst[i] < 0) ? A.nptr[a[i]] + A.dlo[a[i]] : sst[i];
+          const int64_t sp = (PROBE && sst[p] < 0) ? A.nptr[a[p]] + A.dlo[a[p]] : sst[p];
+          k4acc += k4_recompute(A.ncol, a, k, p, si, slen[i], sp, slen[p]);
         }
       }
     }

@@ -33,6 +33,7 @@ void to_public(const Tuning& t, m4_tuning* out) {
   out->c4_light_max = t.c4_light_max;
   out->batch_variant = t.batch_variant;
   out->batch_light = t.batch_light;
+  out->hub_min = t.hub_min;
 }
 
 }  // namespace
@@ -47,12 +48,14 @@ extern "C" int m4_set_tuning(m4_ctx* ctx, const m4_tuning* t) {
   if (!ctx || !t) return M4_EINVAL;
   if (t->tri_wave_max < 2 || t->tri_wave_max > 64 || t->c4_light_max < 1 ||
       t->c4_light_max > C4_HASH_SLOTS / 2 || (t->batch_variant != 0 && t->batch_variant != 1) ||
-      t->batch_light < 1 || t->batch_light > 256)
+      t->batch_light < 1 || t->batch_light > 256 ||
+      (t->hub_min != 0 && (t->hub_min < 4 || t->hub_min > 65536)))
     return set_error(ctx, M4_EINVAL, "tuning value out of range");
   ctx->tune.tri_wave_max = t->tri_wave_max;
   ctx->tune.c4_light_max = t->c4_light_max;
   ctx->tune.batch_variant = t->batch_variant;
   ctx->tune.batch_light = t->batch_light;
+  ctx->tune.hub_min = t->hub_min;
   return M4_OK;
 }
 
@@ -96,6 +99,33 @@ extern "C" int m4_autotune(m4_ctx* ctx, const m4_csr* graph, const m4_batch* bat
             best.c4_light_max = l;
           }
         }
+      // then the hub-table threshold at the chosen bucket bounds
+      const int hub_mins[] = {0, 16, 32, 64, 128};
+      for (int hm : hub_mins) {
+        ctx->tune.hub_min = hm;
+        m4_opts o{};
+        o.tri_wave_max = best.tri_wave_max;
+        o.c4_light_max = best.c4_light_max;
+        uint64_t cnt[6];
+        int rc = m4_count_motifs4_ex(ctx, graph, &o, cnt, nullptr);
+        if (rc == M4_OK && memcmp(ref, cnt, sizeof(ref)) != 0)
+          rc = set_error(ctx, M4_EINTERNAL, "autotune: thresholds changed the counts");
+        double ms = 1e300;
+        for (int r = 0; r < reps && rc == M4_OK; r++) {
+          const double t0 = wall_ms();
+          rc = m4_count_motifs4_ex(ctx, graph, &o, cnt, nullptr);
+          ms = std::min(ms, wall_ms() - t0);
+        }
+        if (rc != M4_OK) {
+          ctx->tune = start;
+          return rc;
+        }
+        if (ms < best_ms) {
+          best_ms = ms;
+          best.hub_min = hm;
+        }
+      }
+      ctx->tune.hub_min = start.hub_min;
     }
     if (batch) {
       const int64_t G = batch->num_graphs;

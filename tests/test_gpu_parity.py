@@ -55,6 +55,24 @@ def test_hub_rows_and_window_counters(ctx):
                              comb(3, 2) * comb(70000, 2), 0, 0)
 
 
+def test_multi_window_long_segments(ctx):
+    # A 70000-cycle below K_{50,200}: the 4-cycle owners (the 50 side) see
+    # their lower neighbours' rows only in the second window of 64K ranks,
+    # and every such visit is longer than 8 entries; the relabelled copy
+    # mixes the two parts in the input ids (not in the degree order).
+    cyc, bip = G.cycle(70000), G.complete_bipartite(50, 200)
+    exp = tuple(a + b for a, b in zip(
+        (0, 70000, 0, 0, 0, 0),
+        (50 * comb(200, 3) + 200 * comb(50, 3), 0, 0, comb(50, 2) * comb(200, 2), 0, 0)))
+    g = G.disjoint_union(cyc, bip)
+    assert ctx.count(*g) == exp
+    perm = np.random.default_rng(3).permutation(len(g[0]) - 1)
+    assert ctx.count(*G.relabel(g, perm)) == exp
+    # hubs whose windows hold both short and long visits, against the oracle
+    h = G.disjoint_union(G.disjoint_union(cyc, bip), gg.ba(3000, 12, 7))
+    assert ctx.count(*h) == oracle.closure(*h)
+
+
 def _random_cases():
     out = []
     for s in range(30):
