@@ -52,7 +52,7 @@ size_t prep_bytes(int64_t n, int64_t nnz) {
   size_t b = 0;
   b += 5 * align256((size_t)n * 4 + 4);
   b += 2 * align256((size_t)(n + 1) * 8);
-  b += align256((size_t)nnz * 4 + 4);
+  b += align256((size_t)(nnz + NCOL_PAD) * 4);
   b += align256((size_t)(nnz / 2) * 4 + 4);
   return b + 4096;
 }
@@ -69,7 +69,7 @@ Prep carve_prep(char* base, int64_t n, int64_t nnz) {
   P.dplus = a.take<int32_t>(n + 1);
   P.nptr = a.take<int64_t>(n + 1);
   P.optr = a.take<int64_t>(n + 1);
-  P.ncol = a.take<int32_t>(nnz + 1);
+  P.ncol = a.take<int32_t>(nnz + NCOL_PAD);
   P.t = a.take<uint32_t>(nnz / 2 + 1);
   return P;
 }

@@ -16,12 +16,15 @@
 // W_u = sum_{v in L(u)} (d(v) - 1):
 //   hash bucket   -- small W_u: one workgroup, open-addressing table in LDS;
 //   window bucket -- large W_u: one 1024-thread workgroup, dense counters in
-//                    LDS over windows of 64K ranks (16-bit counters while
-//                    |L(u)| < 65536, else 32K ranks of 32-bit counters);
-//                    every lower neighbour keeps a cursor into its sorted row
-//                    so each window reads exactly its own endpoints.
+//                    LDS over windows of 128 KiB; a counter is 4 bits wide
+//                    for endpoints of degree <= 15, 8 bits for degree <= 255
+//                    and 32 bits beyond (c_u[w] never exceeds d(w)), so a
+//                    window spans up to 262144 ranks; every lower neighbour
+//                    keeps a cursor into its sorted row so each window reads
+//                    exactly its own endpoints.
 #include <limits.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "m4_device.h"
@@ -47,6 +50,10 @@ struct C4Args {
   uint32_t flags;
   const int64_t* seg_off;  // window owners: first descriptor of each owner
   int4* desc;              // window owners: per-segment cursor descriptors
+  // counter zones of the window owners (ranks >= r1): 4-bit counters for
+  // ranks [r1, z1) (degree <= 15), 8-bit for [z1, z2) (degree <= 255), 32-bit
+  // from z2 on; aw and bw are the words of the first two zones
+  int64_t z1, z2, aw, bw;
 };
 
 // wedge bound of every owner: G lanes cooperate on one row, 4 loads in flight
@@ -83,8 +90,7 @@ __global__ __launch_bounds__(256) void k_c4_plan(const int64_t* __restrict__ npt
     uint32_t k = CB_NONE;
     if (u >= r1 && nl >= 2 && s > 0) {
       if (s <= light_max) k = CB_HASH;
-      else if (nl < 65535) k = CB_WIN16;
-      else k = CB_WIN32;
+      else k = CB_WIN16;
     }
     key[u] = k;
   }
@@ -115,8 +121,7 @@ __global__ __launch_bounds__(1024) void k_c4_plan_big(const int64_t* __restrict_
     uint32_t k = CB_NONE;
     if (u >= r1 && nl >= 2 && tot > 0) {
       if (tot <= light_max) k = CB_HASH;
-      else if (nl < 65535) k = CB_WIN16;
-      else k = CB_WIN32;
+      else k = CB_WIN16;
     }
     key[u] = k;
   }
@@ -253,6 +258,20 @@ __global__ void k_lowcut(const int64_t* __restrict__ nptr, const int32_t* __rest
   lowcut[v] = (int32_t)(lower_index(ncol, nptr[v], rend, (int32_t)r1) - nptr[v]);
 }
 
+// first ranks with degree > 15 and > 255 (degrees are sorted by rank)
+__global__ void k_zone_bounds(const int32_t* __restrict__ dr, int64_t n, int64_t* __restrict__ out) {
+  const int i = threadIdx.x;
+  if (i >= 2) return;
+  const int thr = i == 0 ? 15 : 255;
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (dr[mid] <= thr) lo = mid + 1;
+    else hi = mid;
+  }
+  out[i] = lo;
+}
+
 __global__ void k_c4_heavy_len(const int32_t* __restrict__ order, const int64_t* __restrict__ start,
                                const int32_t* __restrict__ dlo, int32_t* __restrict__ len) {
   const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -260,39 +279,146 @@ __global__ void k_c4_heavy_len(const int32_t* __restrict__ order, const int64_t*
   if (h < H) len[h] = dlo[order[b + h]];
 }
 
-constexpr int W_NT = 1024, W_GL = 8, W_NG = W_NT / W_GL, W_NCH = 8, W_SHORT = 8;
+constexpr int W_NT = 1024, W_GL = 8, W_NG = W_NT / W_GL, W_SHORT = 8;
 constexpr int W_BATCH = 4096;  // segments per pass (bounds the long-visit queue)
+constexpr int W_RPT = W_BATCH / W_NT;  // segments per thread and pass
 
-// One counter update of the window: adds the old value to the running sum
-// of C(c, 2) (every increment of c_u[w] from c to c+1 adds c).
-template <bool NARROW>
-__device__ __forceinline__ uint32_t window_add(uint32_t* cnt, uint32_t o) {
-  if (NARROW) {
-    const uint32_t sh = (o & 1u) << 4;
-    const uint32_t old = atomicAdd(&cnt[o >> 1], 1u << sh);
-    return (old >> sh) & 0xffffu;
+// Counter of rank x (x >= r1) in the zoned layout: a 4-bit counter while the
+// degree of x is <= 15, 8-bit while <= 255, else 32-bit.  c_u[x] counts
+// common neighbours of u and x, so it never exceeds the degree of x and no
+// counter overflows into its neighbour.
+__device__ __forceinline__ void zone_slot(const C4Args& A, int64_t x, int64_t& word, int& shift) {
+  if (x < A.z1) {
+    const int64_t k = x - A.r1;
+    word = k >> 3;
+    shift = (int)(k & 7) * 4;
+  } else if (x < A.z2) {
+    const int64_t k = x - A.z1;
+    word = A.aw + (k >> 2);
+    shift = (int)(k & 3) * 8;
+  } else {
+    word = A.aw + A.bw + (x - A.z2);
+    shift = 0;
   }
-  return atomicAdd(&cnt[o], 1u);
+}
+
+// first rank whose counter lies in word w
+__device__ __forceinline__ int64_t zone_rank(const C4Args& A, int64_t w) {
+  if (w < A.aw) return A.r1 + 8 * w;
+  if (w < A.aw + A.bw) return A.z1 + 4 * (w - A.aw);
+  return A.z2 + (w - A.aw - A.bw);
+}
+
+// words holding the counters of ranks [r1, u)
+__device__ __forceinline__ int64_t zone_words(const C4Args& A, int64_t u) {
+  if (u <= A.r1) return 0;
+  if (u <= A.z1) return (u - A.r1 + 7) >> 3;
+  if (u <= A.z2) return A.aw + ((u - A.z1 + 3) >> 2);
+  return A.aw + A.bw + (u - A.z2);
+}
+
+// one wedge endpoint x of the window starting at word wlo (no value returned:
+// the sum of C(c, 2) is taken from the counters when the window closes)
+__device__ __forceinline__ void window_inc(const C4Args& A, uint32_t* cnt, int64_t wlo,
+                                           int32_t x) {
+  int64_t word;
+  int shift;
+  zone_slot(A, x, word, shift);
+  atomicAdd(&cnt[word - wlo], 1u << shift);
+}
+
+// Adds sum C(c, 2) over the counters in words [wlo, wlo + words) of a closing
+// window and clears them for the next one.
+__device__ __forceinline__ void window_close(const C4Args& A, uint32_t* cnt, int64_t wlo,
+                                             int words, u128_t& acc) {
+  uint64_t s = 0;
+  for (int i = threadIdx.x; i < words; i += W_NT) {
+    const uint32_t w = cnt[i];
+    if (w) {
+      const int64_t gw = wlo + i;
+      if (gw < A.aw) {
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+          const uint64_t c = (w >> (4 * k)) & 0xfu;
+          s += c * (c - 1) / 2;
+        }
+      } else if (gw < A.aw + A.bw) {
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+          const uint64_t c = (w >> (8 * k)) & 0xffu;
+          s += c * (c - 1) / 2;
+        }
+      } else {
+        s += (uint64_t)w * (w - 1) / 2;
+      }
+      cnt[i] = 0;
+    }
+  }
+  acc += s;
 }
 
 __device__ __forceinline__ int32_t row_at(const int32_t* ncol, int64_t i, int64_t e) {
   return i < e ? ncol[i] : INT_MAX;
 }
 
+__device__ __forceinline__ int32_t comp(const int4& v, int r) {
+  return r == 0 ? v.x : (r == 1 ? v.y : (r == 2 ? v.z : v.w));
+}
+
+// A visit of at most 7 entries by one thread: entries c .. c+14 from five
+// aligned 16-byte loads, the entries below hi counted, the descriptor
+// advanced (the new cursor's value and the one 7 later are among them).
+__device__ __forceinline__ int short_visit(const C4Args& A, const int4* __restrict__ ncol4,
+                                           uint32_t* cnt, int4& d, int64_t wlo, int32_t hi) {
+  const int64_t c = d.x, e = d.y, base = c & ~int64_t(3);
+  const int off = (int)(c - base);
+  int4 v[5];
+#pragma unroll
+  for (int q = 0; q < 5; q++) v[q] = ncol4[(base >> 2) + q];
+  int32_t x[W_SHORT + 7];
+#pragma unroll
+  for (int j = 0; j < W_SHORT + 7; j++) {
+    int32_t val;
+    switch (off) {
+      default: val = comp(v[j >> 2], j & 3); break;
+      case 1: val = comp(v[(j + 1) >> 2], (j + 1) & 3); break;
+      case 2: val = comp(v[(j + 2) >> 2], (j + 2) & 3); break;
+      case 3: val = comp(v[(j + 3) >> 2], (j + 3) & 3); break;
+    }
+    x[j] = c + j < e ? val : INT_MAX;
+  }
+  int took = 0;
+#pragma unroll
+  for (int j = 0; j < W_SHORT; j++)
+    if (x[j] < hi) {
+      window_inc(A, cnt, wlo, x[j]);
+      took++;
+    }
+  int32_t z = x[0], w = x[7];
+#pragma unroll
+  for (int j = 1; j < W_SHORT; j++)
+    if (j == took) {
+      z = x[j];
+      w = x[j + 7];
+    }
+  d = make_int4((int)(c + took), (int)e, z, w);
+  return took;
+}
+
 // One heavy owner per workgroup, windows of counters in LDS in order.  A
 // segment is one lower neighbour's row; its descriptor holds the cursor (the
 // first entry not yet counted), the row end, and the values at the cursor and
 // 7 entries after it, so the length of its visit to a window is known to be
-// 0, at most 8, or more without reading the row.  Per pass over W_BATCH
-// segments, every thread first takes whole segments by itself: empty visits
-// cost the descriptor only, short visits (<= 8 entries, most of them) one
-// thread with 8 independent loads; longer visits are queued in LDS and then
-// walked by 8-lane groups, 64 entries per step with the next step's loads in
-// flight.
-template <bool NARROW>
+// 0, at most 7, or more without reading the row.  Rows are read with 16-byte
+// loads aligned below the cursor (entries before the cursor lie below the
+// window, entries from the row end on are masked; the array has slack after
+// its last row).  Per pass over W_BATCH segments, every thread first takes
+// whole segments by itself: an empty visit costs the descriptor only, a
+// short one five 16-byte loads; longer visits are queued in LDS and walked
+// by 8-lane groups, 64 entries (two 16-byte loads per lane) per step with
+// the next queued segment's first step in flight.
 __global__ __launch_bounds__(W_NT) void k_c4_window(C4Args A) {
-  constexpr int WIN = NARROW ? C4_WIN16 : C4_WIN32;
-  constexpr int WORDS = NARROW ? WIN / 2 : WIN;
+  constexpr int WORDS = C4_WIN_WORDS;
   __shared__ uint32_t cnt[WORDS];
   __shared__ int32_t queue[W_BATCH];
   __shared__ int s_item, s_q;
@@ -302,8 +428,11 @@ __global__ __launch_bounds__(W_NT) void k_c4_window(C4Args A) {
   const uint64_t gmask = (1ull << W_GL) - 1;
   const int64_t b0 = A.start[A.bucket], cnt_items = A.start[A.bucket + 1] - b0;
   const int64_t hbase = b0 - A.start[CB_WIN16];
+  const int4* __restrict__ ncol4 = reinterpret_cast<const int4*>(A.ncol);
   u128_t acc = 0;
   unsigned long long wedges = 0, owners = 0, segs = 0, visits = 0;
+  // counters start at zero; every window clears the ones it used
+  for (int i = tid; i < WORDS; i += W_NT) cnt[i] = 0;
   for (;;) {
     if (tid == 0) s_item = (int)atomicAdd(A.work, 1u);
     __syncthreads();
@@ -316,101 +445,121 @@ __global__ __launch_bounds__(W_NT) void k_c4_window(C4Args A) {
     const int64_t so = A.seg_off[hbase + pos];
     const int nl = (int)(A.seg_off[hbase + pos + 1] - so);
     int4* D = A.desc + so;
+    // owners with at most W_BATCH segments keep each thread's descriptors in
+    // registers from window to window
+    const bool resident = nl <= W_BATCH;
+    int4 rdesc[W_RPT];
+    uint32_t stale = (1u << W_RPT) - 1u;
     if (tid == 0) {
       owners++;
       segs += (unsigned long long)nl;
-      visits += (unsigned long long)nl * (unsigned long long)((u - A.r1 + WIN - 1) / WIN);
     }
-    for (int64_t lo = A.r1; lo < u; lo += WIN) {
-      const int32_t hi = (int32_t)(lo + WIN < u ? lo + WIN : u);
-      for (int i = tid; i < WORDS; i += W_NT) cnt[i] = 0;
+    const int64_t uwords = zone_words(A, u);
+    if (tid == 0)
+      visits += (unsigned long long)nl * (unsigned long long)((uwords + WORDS - 1) / WORDS);
+    for (int64_t wlo = 0; wlo < uwords; wlo += WORDS) {
+      const int64_t lo = zone_rank(A, wlo);
+      const int64_t hnext = zone_rank(A, wlo + WORDS);
+      const int32_t hi = (int32_t)(hnext < u ? hnext : u);
       for (int s0 = 0; s0 < nl; s0 += W_BATCH) {
         const int s1 = s0 + W_BATCH < nl ? s0 + W_BATCH : nl;
         if (tid == 0) s_q = 0;
         __syncthreads();
         // ---- whole segments per thread
-        for (int sg = s0 + tid; sg < s1; sg += W_NT) {
-          const int4 d = D[sg];
-          if (d.z >= hi) continue;  // nothing in this window
-          if (d.w < hi) {           // more than 8 entries: queue it
-            queue[atomicAdd(&s_q, 1)] = sg;
-            continue;
-          }
-          const int64_t c = d.x, e = d.y;
-          int32_t x[W_SHORT];
+        if (resident) {
+          // descriptors stay in registers across windows; one that a group
+          // advances (a long visit) is stored before and reloaded after
 #pragma unroll
-          for (int j = 0; j < W_SHORT; j++) x[j] = row_at(A.ncol, c + j, e);
-          int took = 0;
-#pragma unroll
-          for (int j = 0; j < W_SHORT; j++)
-            if (x[j] < hi) {
-              acc += window_add<NARROW>(cnt, (uint32_t)(x[j] - (int32_t)lo));
-              took++;
+          for (int j = 0; j < W_RPT; j++) {
+            const int sg = tid + j * W_NT;
+            if (sg < nl) {
+              if ((stale >> j) & 1u) {
+                rdesc[j] = D[sg];
+                stale &= ~(1u << j);
+              }
+              if (rdesc[j].z < hi) {
+                if (rdesc[j].w < hi) {
+                  D[sg] = rdesc[j];
+                  queue[atomicAdd(&s_q, 1)] = sg;
+                  stale |= 1u << j;
+                } else {
+                  wedges += short_visit(A, ncol4, cnt, rdesc[j], wlo, hi);
+                }
+              }
             }
-          wedges += (unsigned long long)took;
-          // x[took] >= hi exists because the entry 7 after the cursor is >= hi
-          int32_t znext = x[0];
-#pragma unroll
-          for (int j = 1; j < W_SHORT; j++)
-            if (j == took) znext = x[j];
-          D[sg] = make_int4((int)(c + took), (int)e, znext, row_at(A.ncol, c + took + 7, e));
+          }
+        } else {
+          for (int sg = s0 + tid; sg < s1; sg += W_NT) {
+            int4 d = D[sg];
+            if (d.z >= hi) continue;  // nothing in this window
+            if (d.w < hi) {           // 8 entries or more: queue it
+              queue[atomicAdd(&s_q, 1)] = sg;
+              continue;
+            }
+            wedges += short_visit(A, ncol4, cnt, d, wlo, hi);
+            D[sg] = d;
+          }
         }
         __syncthreads();
-        // ---- queued long segments, one 8-lane group each
+        // ---- queued long segments, one 8-lane group each: step k reads the
+        // 64 entries [base + 64k, base + 64k + 64); lane gl holds entries
+        // 4 gl .. 4 gl + 3 and 32 + 4 gl .. 32 + 4 gl + 3 of the step
         const int nq = s_q;
         int qi = g;
         int4 dA = qi < nq ? D[queue[qi]] : make_int4(0, 0, INT_MAX, INT_MAX);
-        int32_t wa[W_NCH];
-#pragma unroll
-        for (int k2 = 0; k2 < W_NCH; k2++) {
-          const int64_t idx = (int64_t)dA.x + gl + W_GL * k2;
-          wa[k2] = qi < nq ? row_at(A.ncol, idx, dA.y) : INT_MAX;
-        }
+        int64_t pA = (int64_t)dA.x & ~int64_t(63);  // first step, aligned to 64 entries
+        int4 a0 = qi < nq ? ncol4[(pA >> 2) + gl] : make_int4(0, 0, 0, 0);
+        int4 a1 = qi < nq ? ncol4[(pA >> 2) + 8 + gl] : make_int4(0, 0, 0, 0);
         while (qi < nq) {  // uniform in the group
           const int sg = queue[qi];
           const int qn = qi + W_NG;
           const int4 dB = qn < nq ? D[queue[qn]] : make_int4(0, 0, INT_MAX, INT_MAX);
-          int32_t wb[W_NCH];
-#pragma unroll
-          for (int k2 = 0; k2 < W_NCH; k2++) {
-            const int64_t idx = (int64_t)dB.x + gl + W_GL * k2;
-            wb[k2] = qn < nq ? row_at(A.ncol, idx, dB.y) : INT_MAX;
-          }
-          int64_t c = dA.x;
-          int32_t vnext = INT_MAX;
+          const int64_t pB = (int64_t)dB.x & ~int64_t(63);
+          int4 b0v = qn < nq ? ncol4[(pB >> 2) + gl] : make_int4(0, 0, 0, 0);
+          int4 b1v = qn < nq ? ncol4[(pB >> 2) + 8 + gl] : make_int4(0, 0, 0, 0);
+          const int64_t c0 = dA.x, e = dA.y;
+          int64_t p = pA;
+          int64_t cend = c0;  // new cursor
           for (;;) {
-            int tot = 0;
-            bool stop = false;
+            // the 8 entries of this lane in this step
+            int32_t xs[8];
+            xs[0] = a0.x; xs[1] = a0.y; xs[2] = a0.z; xs[3] = a0.w;
+            xs[4] = a1.x; xs[5] = a1.y; xs[6] = a1.z; xs[7] = a1.w;
+            int mine = 0;
 #pragma unroll
-            for (int k2 = 0; k2 < W_NCH; k2++) {
-              if (!stop) {
-                const bool in = wa[k2] < hi;
-                if (in) {
-                  acc += window_add<NARROW>(cnt, (uint32_t)(wa[k2] - (int32_t)lo));
-                  wedges++;
-                }
-                // rows are sorted: the entries inside the window are a prefix
-                const int nin = __popcll((__ballot(in) >> gshift) & gmask);
-                tot += nin;
-                if (nin < W_GL) {
-                  vnext = __shfl(wa[k2], gshift + nin, WAVE);
-                  stop = true;
-                }
+            for (int r = 0; r < 8; r++) {
+              const int64_t idx = p + (r < 4 ? 4 * gl + r : 32 + 4 * gl + (r - 4));
+              const bool in = idx >= c0 && idx < e && xs[r] < hi;
+              if (in) {
+                window_inc(A, cnt, wlo, xs[r]);
+                mine++;
               }
             }
-            c += tot;
-            if (stop) break;
+            wedges += (unsigned long long)mine;
+            // entries in the window form a run from the cursor: its length is
+            // the group's total
+            int tot = mine;
 #pragma unroll
-            for (int k2 = 0; k2 < W_NCH; k2++) wa[k2] = row_at(A.ncol, c + gl + W_GL * k2, dA.y);
+            for (int o = 1; o < W_GL; o <<= 1) tot += __shfl_xor(tot, o, WAVE);
+            const int64_t first = p > c0 ? p : c0;
+            cend = first + tot;
+            if (cend < p + 64 || p + 64 >= e) break;  // the run ends in this step
+            p += 64;
+            a0 = ncol4[(p >> 2) + gl];
+            a1 = ncol4[(p >> 2) + 8 + gl];
           }
-          if (gl == 0) D[sg] = make_int4((int)c, dA.y, vnext, row_at(A.ncol, c + 7, dA.y));
+          if (gl == 0)
+            D[sg] = make_int4((int)cend, (int)e, row_at(A.ncol, cend, e), row_at(A.ncol, cend + 7, e));
           qi = qn;
           dA = dB;
-#pragma unroll
-          for (int k2 = 0; k2 < W_NCH; k2++) wa[k2] = wb[k2];
+          pA = pB;
+          a0 = b0v;
+          a1 = b1v;
         }
         __syncthreads();
       }
+      window_close(A, cnt, wlo, (int)(uwords - wlo < WORDS ? uwords - wlo : WORDS), acc);
+      __syncthreads();
     }
   }
   block_add_u128<W_NT>(&A.scal->acc[ACC_C4], acc);
@@ -436,7 +585,7 @@ void c4_run(const Prep& P, const Classes& C, Scal* scal, const Tuning& tu, uint3
   uint32_t* key = tmp.take<uint32_t>(n);
   int32_t* order = tmp.take<int32_t>(n);
   int64_t* rtmp = tmp.take<int64_t>(radix_tmp_elems(n, 2));
-  int64_t* start = tmp.take<int64_t>(8);
+  int64_t* start = tmp.take<int64_t>(CB_N + 3);
   int32_t* hlen = tmp.take<int32_t>(n);
   int64_t* seg_off = tmp.take<int64_t>(n + 1);
   int64_t* stmp = tmp.take<int64_t>(scan_tmp_elems(n));
@@ -459,9 +608,14 @@ void c4_run(const Prep& P, const Classes& C, Scal* scal, const Tuning& tu, uint3
     k_c4_plan_big<<<(unsigned)(n - b4096), 1024, 0, s>>>(P.nptr, P.ncol, P.dr, P.dlo, b4096, C.r1,
                                                          light, wub, key, P.own_lo, P.hi());
   radix_pass(key, nullptr, n, 0, 2, nullptr, order, rtmp, start, s);
-  int64_t hstart[CB_N + 1];
+  k_zone_bounds<<<1, 64, 0, s>>>(P.dr, n, start + CB_N + 1);
+  int64_t hstart[CB_N + 3];
   M4_HIP(hipMemcpyAsync(hstart, start, sizeof(hstart), hipMemcpyDeviceToHost, s));
   M4_HIP(hipStreamSynchronize(s));
+  // counter zones of the window owners
+  const int64_t z1 = std::max<int64_t>(hstart[CB_N + 1], C.r1);
+  const int64_t z2 = std::max<int64_t>(hstart[CB_N + 2], z1);
+  const int64_t aw = (z1 - C.r1 + 7) >> 3, bw = (z2 - z1 + 3) >> 2;
   const int64_t H = hstart[CB_WIN32 + 1] - hstart[CB_WIN16];
   int4* desc = nullptr;
   if (H > 0) {
@@ -494,22 +648,18 @@ void c4_run(const Prep& P, const Classes& C, Scal* scal, const Tuning& tu, uint3
   A.flags = flags;
   A.seg_off = seg_off;
   A.desc = desc;
+  A.z1 = z1;
+  A.z2 = z2;
+  A.aw = aw;
+  A.bw = bw;
   // heavy owners first: one 1024-thread workgroup per CU
   if (hstart[CB_WIN16 + 1] > hstart[CB_WIN16]) {
     A.bucket = CB_WIN16;
     A.slot = M4_K_C4_WIN16;
     A.work = &scal->work[CB_WIN16];
     if (kt) kt->begin(M4_K_C4_WIN16, s);
-    k_c4_window<true><<<(unsigned)num_cu, W_NT, 0, s>>>(A);
+    k_c4_window<<<(unsigned)num_cu, W_NT, 0, s>>>(A);
     if (kt) kt->end(M4_K_C4_WIN16, s);
-  }
-  if (hstart[CB_WIN32 + 1] > hstart[CB_WIN32]) {
-    A.bucket = CB_WIN32;
-    A.slot = M4_K_C4_WIN32;
-    A.work = &scal->work[CB_WIN32];
-    if (kt) kt->begin(M4_K_C4_WIN32, s);
-    k_c4_window<false><<<(unsigned)num_cu, W_NT, 0, s>>>(A);
-    if (kt) kt->end(M4_K_C4_WIN32, s);
   }
   if (hstart[CB_HASH + 1] > hstart[CB_HASH]) {
     A.bucket = CB_HASH;

@@ -32,10 +32,12 @@ enum C4Bucket { CB_NONE = 0, CB_HASH, CB_WIN16, CB_WIN32, CB_N = 4 };
 
 // Largest out-degree handled with the bitmap rows in LDS.
 constexpr int TRI_LDS_MAX = 1024;
-// 4-cycle window widths (16-bit and 32-bit counters, 128 KiB of LDS).
-constexpr int C4_WIN16 = 65536;
-constexpr int C4_WIN32 = 32768;
+// 4-cycle window: 32768 words (128 KiB of LDS) of zoned counters.
+constexpr int C4_WIN_WORDS = 32768;
 constexpr int C4_HASH_SLOTS = 4096;
+// Entries of slack after the last row of a rank-space CSR, so that 16-byte
+// vector loads aligned below a cursor may run past the end of the array.
+constexpr int NCOL_PAD = 64;
 
 struct Scal {
   U128 acc[ACC_N + 1];

@@ -325,7 +325,7 @@ int count_partitioned(m4_ctx* c, const m4_csr* g, const m4_opts* o, uint64_t out
     D.used = fixed_used;
     int64_t* dpairs = D.take<int64_t>(2 * rows.size() + 2);
     int32_t* dlens = D.take<int32_t>(rows.size() + 1);
-    int32_t* dcol = D.take<int32_t>(ent + 1);
+    int32_t* dcol = D.take<int32_t>(ent + NCOL_PAD);
     Pinned& S = PS.stage[parts & 1];
     const size_t sb = al((2 * rows.size() + 2) * 8) + al((rows.size() + 1) * 4) + al(ent * 4 + 4);
     S.ensure(sb);

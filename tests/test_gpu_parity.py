@@ -56,13 +56,15 @@ def test_hub_rows_and_window_counters(ctx):
 
 
 def test_multi_window_long_segments(ctx):
-    # A 70000-cycle below K_{50,200}: the 4-cycle owners (the 50 side) see
-    # their lower neighbours' rows only in the second window of 64K ranks,
-    # and every such visit is longer than 8 entries; the relabelled copy
-    # mixes the two parts in the input ids (not in the degree order).
-    cyc, bip = G.cycle(70000), G.complete_bipartite(50, 200)
+    # A 300000-cycle below K_{50,200}: the cycle's degree-2 ranks fill more
+    # than one window of 4-bit counters (262144 per window), so the 4-cycle
+    # owners (the 50 side) see their lower neighbours' rows only in the
+    # second window, and every such visit is longer than 8 entries; the
+    # relabelled copy mixes the two parts in the input ids (not in the
+    # degree order).
+    cyc, bip = G.cycle(300000), G.complete_bipartite(50, 200)
     exp = tuple(a + b for a, b in zip(
-        (0, 70000, 0, 0, 0, 0),
+        (0, 300000, 0, 0, 0, 0),
         (50 * comb(200, 3) + 200 * comb(50, 3), 0, 0, comb(50, 2) * comb(200, 2), 0, 0)))
     g = G.disjoint_union(cyc, bip)
     assert ctx.count(*g) == exp

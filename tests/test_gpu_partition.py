@@ -76,3 +76,15 @@ def test_partition_budget_too_small_is_an_error(ctx):
     with pytest.raises(m4.M4Error) as e:
         ctx.count(*g, flags=m4.M4_FORCE_PARTITION, budget=4096)
     assert e.value.code == m4.M4_ENOMEM
+
+
+def test_web_rmat_under_budget(ctx):
+    # web-like R-MAT (the skew of the scale-24 web workload at scale 19),
+    # resident and under a budget that holds about a third of the rows
+    g = gg.rmat(19, 16, 0.45, 0.22, 0.22, 4)
+    ref, rst = ctx.count(*g, stats=True)
+    got, st = ctx.count(*g, budget=budget_for(g, 3), stats=True)
+    assert got == ref
+    assert st["partitions"] >= 3 and st["h2d_bytes"] > 0
+    for k in ("T", "K4", "C4_ni", "D_ni"):
+        assert st[k] == rst[k], k
