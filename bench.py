@@ -46,8 +46,8 @@ KERNEL_SYMBOL = {
     "tri_global": "k_tri_global", "tri_1024": "k_tri_lds<1024, 256>",
     "tri_512": "k_tri_lds<512, 256>", "tri_256": "k_tri_lds<256, 256>",
     "tri_128": "k_tri_lds<128, 256>", "tri_wave": "k_tri_lds<64, 64>",
-    "c4_win16": "k_c4_window<true>", "c4_win32": "k_c4_window<false>",
-    "c4_hash": "k_c4_hash", "closure": "k_closure", "c4_plan": "k_c4_plan",
+    "c4_window": "k_c4_window", "c4_med": "k_c4_hash<1024, 16384, 4>",
+    "c4_hash": "k_c4_hash<256, 4096, 4>", "closure": "k_closure", "c4_plan": "k_c4_plan",
     "build": "(CSR builder kernels)",
 }
 

@@ -78,7 +78,8 @@ typedef struct {
   /* tuning (0 = library default / autotuned value) */
   int32_t tri_wave_max;   /* owners with out-degree <= this use one wavefront      */
   int32_t c4_light_max;   /* owners with wedge bound <= this use the LDS hash      */
-  int32_t reserved[4];
+  int32_t c4_med_max;     /* ... <= this the medium LDS hash (-1: none)            */
+  int32_t reserved[3];
 } m4_opts;
 
 /* Kernel slots of m4_stats.ms_kernel / k_* (one slot per kernel launch of
@@ -92,9 +93,9 @@ enum {
   M4_K_TRI_128,       /* ... (wave max, 128]                                   */
   M4_K_TRI_WAVE,      /* ... out-degree <= 64, one wavefront per owner         */
   M4_K_C4_PLAN,       /* 4-cycle wedge bounds and owner buckets                 */
-  M4_K_C4_WIN16,      /* 4-cycle owners with windowed 16-bit LDS counters      */
-  M4_K_C4_WIN32,      /* ... windowed 32-bit LDS counters                      */
-  M4_K_C4_HASH,       /* ... LDS hash table                                    */
+  M4_K_C4_WINDOW,     /* 4-cycle owners with windows of dense LDS counters     */
+  M4_K_C4_MED,        /* ... medium wedge bound, 16384-slot LDS hash table     */
+  M4_K_C4_HASH,       /* ... small wedge bound, 4096-slot LDS hash table       */
   M4_K_CLOSURE,       /* closure sums and exact inverse                         */
   M4_K_TRI_HUBS,      /* hub tables of the long out-lists (triangle probes)     */
   M4_NK = 16
@@ -180,7 +181,11 @@ typedef struct {
                             probes it for its later out-neighbours instead of
                             scanning the list when that is cheaper (0 = never,
                             else 4..65536, default 32)                        */
-  int32_t reserved[3];
+  int32_t c4_med_max;    /* single graph: owners with wedge bound in
+                            (c4_light_max, c4_med_max] use the 16384-slot LDS
+                            hash, heavier ones the counter windows (0 = none,
+                            else up to 12288, default 12288)                 */
+  int32_t reserved[2];
 } m4_tuning;
 
 int m4_get_tuning(const m4_ctx* ctx, m4_tuning* out);

@@ -24,7 +24,7 @@ M4_VALIDATE, M4_NO_CACHE, M4_FORCE_PARTITION, M4_STATS, M4_TIMING = 0x1, 0x2, 0x
 M4_PLAIN_LOOP = 0x20
 M4_NK = 16
 KERNELS = ("build", "tri_global", "tri_1024", "tri_512", "tri_256", "tri_128", "tri_wave",
-           "c4_plan", "c4_win16", "c4_win32", "c4_hash", "closure", "tri_hubs")
+           "c4_plan", "c4_window", "c4_med", "c4_hash", "closure", "tri_hubs")
 NAMES = ("star", "path", "paw", "cycle", "diamond", "clique")
 BASIS = ("T", "K4", "C4_ni", "S", "P_ni", "Paw_ni", "D_ni", "sum_t")
 
@@ -45,7 +45,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("device_budget_bytes", ctypes.c_uint64), ("flags", ctypes.c_uint32),
                 ("cache_rows", ctypes.c_uint32), ("hip_stream", ctypes.c_void_p),
                 ("tri_wave_max", ctypes.c_int32), ("c4_light_max", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("c4_med_max", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class Stats(ctypes.Structure):
@@ -77,10 +77,11 @@ class Batch(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("tri_wave_max", ctypes.c_int32), ("c4_light_max", ctypes.c_int32),
                 ("batch_variant", ctypes.c_int32), ("batch_light", ctypes.c_int32),
-                ("hub_min", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("hub_min", ctypes.c_int32), ("c4_med_max", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
     def to_dict(self):
-        return {f: int(getattr(self, f)) for f, _ in self._fields_[:5]}
+        return {f: int(getattr(self, f)) for f, _ in self._fields_[:6]}
 
 
 class Result(ctypes.Structure):
@@ -168,7 +169,8 @@ def make_csr(row_ptr, col, keep: _Keep) -> Csr:
     return Csr(len(rp) - 1, c.size, rp.ctypes.data, c.ctypes.data if c.size else None, 0)
 
 
-def make_opts(flags=0, budget=0, cache_rows=0, stream=None, tri_wave_max=0, c4_light_max=0) -> Opts:
+def make_opts(flags=0, budget=0, cache_rows=0, stream=None, tri_wave_max=0, c4_light_max=0,
+              c4_med_max=0) -> Opts:
     o = Opts()
     o.device_budget_bytes = int(budget)
     o.flags = int(flags)
@@ -176,6 +178,7 @@ def make_opts(flags=0, budget=0, cache_rows=0, stream=None, tri_wave_max=0, c4_l
     o.hip_stream = stream
     o.tri_wave_max = int(tri_wave_max)
     o.c4_light_max = int(c4_light_max)
+    o.c4_med_max = int(c4_med_max)
     return o
 
 
@@ -216,14 +219,15 @@ class Context:
         return None
 
     def count(self, row_ptr, col, *, flags=0, budget=0, cache_rows=0, stream=None,
-              tri_wave_max=0, c4_light_max=0, stats=False, timing=False):
+              tri_wave_max=0, c4_light_max=0, c4_med_max=0, stats=False, timing=False):
         """Six counts; with stats=True (work counters) or timing=True (per
-        kernel HIP-event times) also the m4_stats dict."""
+        kernel HIP-event times) also the m4_stats dict.  Threshold arguments
+        of 0 keep the context's tuning (c4_med_max=-1: no medium bucket)."""
         keep = _Keep()
         g = make_csr(row_ptr, col, keep)
         fl = flags | (M4_STATS if stats else 0) | (M4_TIMING if timing else 0)
         o = make_opts(fl, budget, cache_rows, self._stream_for(row_ptr, stream), tri_wave_max,
-                      c4_light_max)
+                      c4_light_max, c4_med_max)
         out = (ctypes.c_uint64 * 6)()
         st = Stats()
         self._check(lib().m4_count_motifs4_ex(self.h, ctypes.byref(g), ctypes.byref(o),

@@ -203,8 +203,11 @@ Tuning tuning_for(const m4_ctx* c, const m4_opts* o) {
   Tuning tu = c->tune;
   if (o && o->tri_wave_max > 0) tu.tri_wave_max = o->tri_wave_max;
   if (o && o->c4_light_max > 0) tu.c4_light_max = o->c4_light_max;
-  // the hash bucket's table holds C4_HASH_SLOTS keys at load <= 1/2
+  if (o && o->c4_med_max != 0) tu.c4_med_max = o->c4_med_max < 0 ? 0 : o->c4_med_max;
+  // the hash tables hold C4_HASH_SLOTS keys at load <= 1/2 and C4_MED_SLOTS
+  // keys at load <= 3/4
   tu.c4_light_max = std::max(0, std::min(tu.c4_light_max, C4_HASH_SLOTS / 2));
+  tu.c4_med_max = std::max(0, std::min(tu.c4_med_max, 3 * C4_MED_SLOTS / 4));
   return tu;
 }
 

@@ -14,7 +14,9 @@
 // Vertices of degree <= 1 have rank < r1 and never contribute (c <= 1), so
 // endpoints below r1 are skipped.  Owners are split by the wedge bound
 // W_u = sum_{v in L(u)} (d(v) - 1):
-//   hash bucket   -- small W_u: one workgroup, open-addressing table in LDS;
+//   hash bucket   -- small W_u: 256 threads, 4096-slot open-addressing
+//                    table in LDS;
+//   medium bucket -- W_u up to 3/4 of 16384: 1024 threads, 16384-slot table;
 //   window bucket -- large W_u: one 1024-thread workgroup, dense counters in
 //                    LDS over windows of 128 KiB; a counter is 4 bits wide
 //                    for endpoints of degree <= 15, 8 bits for degree <= 255
@@ -22,6 +24,8 @@
 //                    window spans up to 262144 ranks; every lower neighbour
 //                    keeps a cursor into its sorted row so each window reads
 //                    exactly its own endpoints.
+// A table costs per wedge; a window costs per rank of the owner's range, so
+// owners whose endpoints are sparse over many windows belong in a table.
 #include <limits.h>
 
 #include <algorithm>
@@ -53,8 +57,15 @@ struct C4Args {
   // counter zones of the window owners (ranks >= r1): 4-bit counters for
   // ranks [r1, z1) (degree <= 15), 8-bit for [z1, z2) (degree <= 255), 32-bit
   // from z2 on; aw and bw are the words of the first two zones
-  int64_t z1, z2, aw, bw;
+  int32_t z1, z2, aw, bw, zr1;  // zr1: r1 as a 32-bit rank
 };
+
+// bucket of an owner with wedge bound w > 0
+__device__ __forceinline__ uint32_t c4_bucket(int64_t w, int light_max, int med_max) {
+  if (w <= light_max) return CB_HASH;
+  if (w <= med_max) return CB_MED;
+  return CB_WIN;
+}
 
 // wedge bound of every owner: G lanes cooperate on one row, 4 loads in flight
 template <int G>
@@ -63,7 +74,7 @@ __global__ __launch_bounds__(256) void k_c4_plan(const int64_t* __restrict__ npt
                                                  const int32_t* __restrict__ dr,
                                                  const int32_t* __restrict__ dlo, int64_t r_lo,
                                                  int64_t r_hi, int64_t r1, int light_max,
-                                                 int64_t* __restrict__ wub,
+                                                 int med_max, int64_t* __restrict__ wub,
                                                  uint32_t* __restrict__ key, int64_t own_lo,
                                                  int64_t own_hi) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -88,10 +99,7 @@ __global__ __launch_bounds__(256) void k_c4_plan(const int64_t* __restrict__ npt
   if (ok && j == 0) {
     wub[u] = s;
     uint32_t k = CB_NONE;
-    if (u >= r1 && nl >= 2 && s > 0) {
-      if (s <= light_max) k = CB_HASH;
-      else k = CB_WIN16;
-    }
+    if (u >= r1 && nl >= 2 && s > 0) k = c4_bucket(s, light_max, med_max);
     key[u] = k;
   }
 }
@@ -101,7 +109,7 @@ __global__ __launch_bounds__(1024) void k_c4_plan_big(const int64_t* __restrict_
                                                       const int32_t* __restrict__ ncol,
                                                       const int32_t* __restrict__ dr,
                                                       const int32_t* __restrict__ dlo, int64_t r_lo,
-                                                      int64_t r1, int light_max,
+                                                      int64_t r1, int light_max, int med_max,
                                                       int64_t* __restrict__ wub,
                                                       uint32_t* __restrict__ key, int64_t own_lo,
                                                       int64_t own_hi) {
@@ -119,32 +127,36 @@ __global__ __launch_bounds__(1024) void k_c4_plan_big(const int64_t* __restrict_
   if (threadIdx.x == 0) {
     wub[u] = tot;
     uint32_t k = CB_NONE;
-    if (u >= r1 && nl >= 2 && tot > 0) {
-      if (tot <= light_max) k = CB_HASH;
-      else k = CB_WIN16;
-    }
+    if (u >= r1 && nl >= 2 && tot > 0) k = c4_bucket(tot, light_max, med_max);
     key[u] = k;
   }
 }
 
-// ---------------------------------------------------------- hash bucket
-constexpr int H_NT = 256, H_SLOTS = C4_HASH_SLOTS, H_CHUNK = H_NT;
-
-__global__ __launch_bounds__(H_NT) void k_c4_hash(C4Args A) {
-  __shared__ int32_t hkey[H_SLOTS];
-  __shared__ uint32_t hcnt[H_SLOTS];
-  __shared__ int32_t sst[H_CHUNK];
-  __shared__ int32_t spref[H_CHUNK + 1];
+// --------------------------------------------------------- hash buckets
+// One owner at a time per workgroup: the wedge endpoints of the chunk of NT
+// lower neighbours are flattened (a scan of the row lengths), every thread
+// takes UNR endpoints per round with their loads in flight together, and
+// counts them in an open-addressing table in LDS (linear probing, keys
+// inserted with compare-and-swap).  The table is sized to a power of two of
+// at least twice the wedge bound (capped at SLOTS): the number of distinct
+// endpoints never exceeds the wedge bound, which the planner keeps below
+// SLOTS, so a probe always ends.
+template <int NT, int SLOTS, int UNR>
+__global__ __launch_bounds__(NT) void k_c4_hash(C4Args A) {
+  __shared__ int32_t hkey[SLOTS];
+  __shared__ uint32_t hcnt[SLOTS];
+  __shared__ int32_t sst[NT];
+  __shared__ int32_t spref[NT + 1];
   __shared__ int s_item;
   const int tid = threadIdx.x;
   const int64_t b0 = A.start[A.bucket], cnt = A.start[A.bucket + 1] - b0;
   u128_t acc = 0;
   unsigned long long wedges = 0, owners = 0, segs = 0, reads = 0;
-  for (int i = tid; i < H_SLOTS; i += H_NT) {
+  for (int i = tid; i < SLOTS; i += NT) {
     hkey[i] = -1;
     hcnt[i] = 0;
   }
-  constexpr int GRAB = 8;
+  const int GRAB = NT >= 1024 ? 1 : 8;
   int64_t item = 0, last = 0;
   for (;;) {
     if (item == last) {
@@ -161,15 +173,15 @@ __global__ __launch_bounds__(H_NT) void k_c4_hash(C4Args A) {
     const int64_t base = A.nptr[u];
     int64_t wb = A.wub[u];
     int S = 64;
-    while (S < 2 * wb && S < H_SLOTS) S <<= 1;
+    while (S < 2 * wb && S < SLOTS) S <<= 1;
     const uint32_t mask = (uint32_t)S - 1;
     const int shift = 32 - __ffs(S) + 1;
     if (tid == 0) {
       owners++;
       segs += (unsigned long long)nl;
     }
-    for (int c0 = 0; c0 < nl; c0 += H_CHUNK) {
-      const int nc = nl - c0 < H_CHUNK ? nl - c0 : H_CHUNK;
+    for (int c0 = 0; c0 < nl; c0 += NT) {
+      const int nc = nl - c0 < NT ? nl - c0 : NT;
       int len = 0;
       if (tid < nc) {
         int32_t v = A.ncol[base + c0 + tid];
@@ -177,44 +189,58 @@ __global__ __launch_bounds__(H_NT) void k_c4_hash(C4Args A) {
         len = A.row_len ? A.row_len[v] : A.dr[v];
       }
       int64_t tot;
-      int64_t ex = block_excl_scan64<H_NT>(len, &tot);
+      int64_t ex = block_excl_scan64<NT>(len, &tot);
       if (tid < nc) spref[tid] = (int32_t)ex;
       if (tid == 0) spref[nc] = (int32_t)tot;
       __syncthreads();
       const int total = (int)tot;
       if (tid == 0) reads += (unsigned long long)total;
-      for (int q = tid; q < total; q += H_NT) {
-        int si = upper_index(spref, nc, q);
-        int32_t w = A.ncol[sst[si] + (q - spref[si])];
-        if (w < A.r1 || w >= u) continue;
-        uint32_t h = ((uint32_t)w * 0x9E3779B1u) >> shift;
-        for (;;) {
-          int32_t k = hkey[h];
-          if (k == w) break;
-          if (k == -1) {
-            int32_t prev = atomicCAS(&hkey[h], -1, w);
-            if (prev == -1 || prev == w) break;
+      for (int q0 = 0; q0 < total; q0 += NT * UNR) {
+        int32_t w[UNR];
+#pragma unroll
+        for (int j = 0; j < UNR; j++) {
+          const int q = q0 + j * NT + tid;
+          w[j] = INT_MAX;
+          if (q < total) {
+            const int si = upper_index(spref, nc, q);
+            w[j] = A.ncol[sst[si] + (q - spref[si])];
           }
-          h = (h + 1) & mask;
         }
-        acc += atomicAdd(&hcnt[h], 1u);
-        wedges++;
+        uint64_t part = 0;
+#pragma unroll
+        for (int j = 0; j < UNR; j++) {
+          const int32_t x = w[j];
+          if (x < A.r1 || x >= u) continue;
+          uint32_t h = ((uint32_t)x * 0x9E3779B1u) >> shift;
+          for (;;) {
+            int32_t k = hkey[h];
+            if (k == x) break;
+            if (k == -1) {
+              int32_t prev = atomicCAS(&hkey[h], -1, x);
+              if (prev == -1 || prev == x) break;
+            }
+            h = (h + 1) & mask;
+          }
+          part += atomicAdd(&hcnt[h], 1u);
+          wedges++;
+        }
+        acc += part;
       }
       __syncthreads();
     }
-    for (int i = tid; i < S; i += H_NT) {
+    for (int i = tid; i < S; i += NT) {
       hkey[i] = -1;
       hcnt[i] = 0;
     }
     __syncthreads();
   }
-  block_add_u128<H_NT>(&A.scal->acc[ACC_C4], acc);
+  block_add_u128<NT>(&A.scal->acc[ACC_C4], acc);
   if (A.flags & M4_STATS) {
-    block_add_u64<H_NT>(&A.scal->stat[ST_WEDGES], wedges);
-    block_add_u64<H_NT>(&A.scal->kstat[A.slot][0], wedges);
-    block_add_u64<H_NT>(&A.scal->kstat[A.slot][1], owners);
-    block_add_u64<H_NT>(&A.scal->kstat[A.slot][2], segs);
-    block_add_u64<H_NT>(&A.scal->kstat[A.slot][3], reads);
+    block_add_u64<NT>(&A.scal->stat[ST_WEDGES], wedges);
+    block_add_u64<NT>(&A.scal->kstat[A.slot][0], wedges);
+    block_add_u64<NT>(&A.scal->kstat[A.slot][1], owners);
+    block_add_u64<NT>(&A.scal->kstat[A.slot][2], segs);
+    block_add_u64<NT>(&A.scal->kstat[A.slot][3], reads);
   }
 }
 
@@ -234,7 +260,7 @@ __global__ __launch_bounds__(256) void k_c4_desc(const int32_t* __restrict__ ord
                                                  const int32_t* __restrict__ row_len, int64_t r1,
                                                  int4* __restrict__ desc) {
   const int64_t h = blockIdx.x;
-  const int32_t u = order[start[CB_WIN16] + h];
+  const int32_t u = order[start[CB_WIN] + h];
   const int64_t so = seg_off[h], base = nptr[u];
   const int nl = dlo[u];
   for (int i = threadIdx.x; i < nl; i += 256) {
@@ -275,27 +301,28 @@ __global__ void k_zone_bounds(const int32_t* __restrict__ dr, int64_t n, int64_t
 __global__ void k_c4_heavy_len(const int32_t* __restrict__ order, const int64_t* __restrict__ start,
                                const int32_t* __restrict__ dlo, int32_t* __restrict__ len) {
   const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t b = start[CB_WIN16], H = start[CB_WIN32 + 1] - b;
+  const int64_t b = start[CB_WIN], H = start[CB_WIN + 1] - b;
   if (h < H) len[h] = dlo[order[b + h]];
 }
 
 constexpr int W_NT = 1024, W_GL = 8, W_NG = W_NT / W_GL, W_SHORT = 8;
-constexpr int W_BATCH = 4096;  // segments per pass (bounds the long-visit queue)
+constexpr int W_LD = 2;  // 16-byte loads per lane and step of a long visit
+constexpr int W_BATCH = 2048;  // segments per pass (bounds the long-visit queue)
 constexpr int W_RPT = W_BATCH / W_NT;  // segments per thread and pass
 
 // Counter of rank x (x >= r1) in the zoned layout: a 4-bit counter while the
 // degree of x is <= 15, 8-bit while <= 255, else 32-bit.  c_u[x] counts
 // common neighbours of u and x, so it never exceeds the degree of x and no
 // counter overflows into its neighbour.
-__device__ __forceinline__ void zone_slot(const C4Args& A, int64_t x, int64_t& word, int& shift) {
+__device__ __forceinline__ void zone_slot(const C4Args& A, int32_t x, int32_t& word, int& shift) {
   if (x < A.z1) {
-    const int64_t k = x - A.r1;
+    const int32_t k = x - A.zr1;
     word = k >> 3;
-    shift = (int)(k & 7) * 4;
+    shift = (k & 7) * 4;
   } else if (x < A.z2) {
-    const int64_t k = x - A.z1;
+    const int32_t k = x - A.z1;
     word = A.aw + (k >> 2);
-    shift = (int)(k & 3) * 8;
+    shift = (k & 3) * 8;
   } else {
     word = A.aw + A.bw + (x - A.z2);
     shift = 0;
@@ -303,58 +330,39 @@ __device__ __forceinline__ void zone_slot(const C4Args& A, int64_t x, int64_t& w
 }
 
 // first rank whose counter lies in word w
-__device__ __forceinline__ int64_t zone_rank(const C4Args& A, int64_t w) {
-  if (w < A.aw) return A.r1 + 8 * w;
+__device__ __forceinline__ int32_t zone_rank(const C4Args& A, int32_t w) {
+  if (w < A.aw) return A.zr1 + 8 * w;
   if (w < A.aw + A.bw) return A.z1 + 4 * (w - A.aw);
   return A.z2 + (w - A.aw - A.bw);
 }
 
 // words holding the counters of ranks [r1, u)
-__device__ __forceinline__ int64_t zone_words(const C4Args& A, int64_t u) {
-  if (u <= A.r1) return 0;
-  if (u <= A.z1) return (u - A.r1 + 7) >> 3;
+__device__ __forceinline__ int32_t zone_words(const C4Args& A, int32_t u) {
+  if (u <= A.zr1) return 0;
+  if (u <= A.z1) return (u - A.zr1 + 7) >> 3;
   if (u <= A.z2) return A.aw + ((u - A.z1 + 3) >> 2);
   return A.aw + A.bw + (u - A.z2);
 }
 
-// one wedge endpoint x of the window starting at word wlo (no value returned:
-// the sum of C(c, 2) is taken from the counters when the window closes)
-__device__ __forceinline__ void window_inc(const C4Args& A, uint32_t* cnt, int64_t wlo,
-                                           int32_t x) {
-  int64_t word;
+// one wedge endpoint x of the window starting at word wlo: returns the old
+// count c (every increment of c_u[x] from c to c + 1 adds c to the sum of
+// C(c_u[x], 2))
+__device__ __forceinline__ uint32_t window_inc(const C4Args& A, uint32_t* cnt, int32_t wlo,
+                                               int32_t x) {
+  int32_t word;
   int shift;
   zone_slot(A, x, word, shift);
-  atomicAdd(&cnt[word - wlo], 1u << shift);
+  const uint32_t mask = x < A.z1 ? 0xfu : (x < A.z2 ? 0xffu : 0xffffffffu);
+  const uint32_t old = atomicAdd(&cnt[word - wlo], 1u << shift);
+  return (old >> shift) & mask;
 }
 
-// Adds sum C(c, 2) over the counters in words [wlo, wlo + words) of a closing
-// window and clears them for the next one.
-__device__ __forceinline__ void window_close(const C4Args& A, uint32_t* cnt, int64_t wlo,
-                                             int words, u128_t& acc) {
-  uint64_t s = 0;
-  for (int i = threadIdx.x; i < words; i += W_NT) {
-    const uint32_t w = cnt[i];
-    if (w) {
-      const int64_t gw = wlo + i;
-      if (gw < A.aw) {
-#pragma unroll
-        for (int k = 0; k < 8; k++) {
-          const uint64_t c = (w >> (4 * k)) & 0xfu;
-          s += c * (c - 1) / 2;
-        }
-      } else if (gw < A.aw + A.bw) {
-#pragma unroll
-        for (int k = 0; k < 4; k++) {
-          const uint64_t c = (w >> (8 * k)) & 0xffu;
-          s += c * (c - 1) / 2;
-        }
-      } else {
-        s += (uint64_t)w * (w - 1) / 2;
-      }
-      cnt[i] = 0;
-    }
-  }
-  acc += s;
+// word holding the counter of rank x (x >= r1)
+__device__ __forceinline__ int32_t zone_word(const C4Args& A, int32_t x) {
+  int32_t word;
+  int shift;
+  zone_slot(A, x, word, shift);
+  return word;
 }
 
 __device__ __forceinline__ int32_t row_at(const int32_t* ncol, int64_t i, int64_t e) {
@@ -369,7 +377,8 @@ __device__ __forceinline__ int32_t comp(const int4& v, int r) {
 // aligned 16-byte loads, the entries below hi counted, the descriptor
 // advanced (the new cursor's value and the one 7 later are among them).
 __device__ __forceinline__ int short_visit(const C4Args& A, const int4* __restrict__ ncol4,
-                                           uint32_t* cnt, int4& d, int64_t wlo, int32_t hi) {
+                                           uint32_t* cnt, int4& d, int32_t wlo, int32_t hi,
+                                           u128_t& acc) {
   const int64_t c = d.x, e = d.y, base = c & ~int64_t(3);
   const int off = (int)(c - base);
   int4 v[5];
@@ -388,12 +397,14 @@ __device__ __forceinline__ int short_visit(const C4Args& A, const int4* __restri
     x[j] = c + j < e ? val : INT_MAX;
   }
   int took = 0;
+  uint64_t part = 0;
 #pragma unroll
   for (int j = 0; j < W_SHORT; j++)
     if (x[j] < hi) {
-      window_inc(A, cnt, wlo, x[j]);
+      part += window_inc(A, cnt, wlo, x[j]);
       took++;
     }
+  acc += part;
   int32_t z = x[0], w = x[7];
 #pragma unroll
   for (int j = 1; j < W_SHORT; j++)
@@ -405,33 +416,36 @@ __device__ __forceinline__ int short_visit(const C4Args& A, const int4* __restri
   return took;
 }
 
-// One heavy owner per workgroup, windows of counters in LDS in order.  A
-// segment is one lower neighbour's row; its descriptor holds the cursor (the
-// first entry not yet counted), the row end, and the values at the cursor and
-// 7 entries after it, so the length of its visit to a window is known to be
-// 0, at most 7, or more without reading the row.  Rows are read with 16-byte
-// loads aligned below the cursor (entries before the cursor lie below the
-// window, entries from the row end on are masked; the array has slack after
-// its last row).  Per pass over W_BATCH segments, every thread first takes
-// whole segments by itself: an empty visit costs the descriptor only, a
-// short one five 16-byte loads; longer visits are queued in LDS and walked
-// by 8-lane groups, 64 entries (two 16-byte loads per lane) per step with
-// the next queued segment's first step in flight.
+// One heavy owner per workgroup, windows of counters in LDS in rank order.
+// A segment is one lower neighbour's row; its descriptor holds the cursor
+// (the first entry not yet counted), the row end, and the values at the
+// cursor and 7 entries after it, so the length of its visit to a window is
+// known to be 0, at most 7, or more without reading the row.  Rows are read
+// with 16-byte loads aligned below the cursor (entries before the cursor lie
+// below the window, entries from the row end on are masked; the array has
+// slack after its last row).  Per pass over W_BATCH segments every thread
+// first takes whole segments by itself (an empty visit costs nothing for
+// descriptors held in registers, a short one five 16-byte loads); longer
+// visits are queued in LDS and walked by 8-lane groups, 64 entries (two
+// 16-byte loads per lane) per step, with the next queued segment's first
+// step in flight.  The next window starts at the smallest value any cursor
+// points at, so windows without endpoints are never visited.
 __global__ __launch_bounds__(W_NT) void k_c4_window(C4Args A) {
   constexpr int WORDS = C4_WIN_WORDS;
+  constexpr int STEP = 4 * W_GL * W_LD;
+  static_assert(STEP <= NCOL_PAD, "a step may read STEP entries past a cursor");
   __shared__ uint32_t cnt[WORDS];
   __shared__ int32_t queue[W_BATCH];
-  __shared__ int s_item, s_q;
-  const int tid = threadIdx.x, lane = tid & (WAVE - 1);
+  __shared__ int s_item, s_q, s_minz;
+  const int tid = threadIdx.x;
   const int g = tid / W_GL, gl = tid & (W_GL - 1);
-  const int gshift = lane & ~(W_GL - 1);
-  const uint64_t gmask = (1ull << W_GL) - 1;
   const int64_t b0 = A.start[A.bucket], cnt_items = A.start[A.bucket + 1] - b0;
-  const int64_t hbase = b0 - A.start[CB_WIN16];
+  const int64_t hbase = b0 - A.start[CB_WIN];
   const int4* __restrict__ ncol4 = reinterpret_cast<const int4*>(A.ncol);
+  const int4 kNone = make_int4(0, 0, INT_MAX, INT_MAX);
   u128_t acc = 0;
   unsigned long long wedges = 0, owners = 0, segs = 0, visits = 0;
-  // counters start at zero; every window clears the ones it used
+  // counters start at zero; every window clears the words it used
   for (int i = tid; i < WORDS; i += W_NT) cnt[i] = 0;
   for (;;) {
     if (tid == 0) s_item = (int)atomicAdd(A.work, 1u);
@@ -454,18 +468,22 @@ __global__ __launch_bounds__(W_NT) void k_c4_window(C4Args A) {
       owners++;
       segs += (unsigned long long)nl;
     }
-    const int64_t uwords = zone_words(A, u);
-    if (tid == 0)
-      visits += (unsigned long long)nl * (unsigned long long)((uwords + WORDS - 1) / WORDS);
-    for (int64_t wlo = 0; wlo < uwords; wlo += WORDS) {
-      const int64_t lo = zone_rank(A, wlo);
-      const int64_t hnext = zone_rank(A, wlo + WORDS);
+    const int32_t uwords = zone_words(A, u);
+    int32_t wlo = 0;
+    while (wlo < uwords) {
+      // ranks past the last word of a zone map beyond the owner: hi = u
+      const int32_t hnext = wlo + WORDS >= uwords ? u : zone_rank(A, wlo + WORDS);
       const int32_t hi = (int32_t)(hnext < u ? hnext : u);
+      if (tid == 0) {
+        visits += (unsigned long long)nl;
+        s_minz = INT_MAX;
+      }
       for (int s0 = 0; s0 < nl; s0 += W_BATCH) {
         const int s1 = s0 + W_BATCH < nl ? s0 + W_BATCH : nl;
         if (tid == 0) s_q = 0;
         __syncthreads();
         // ---- whole segments per thread
+        int32_t zmin = INT_MAX;
         if (resident) {
           // descriptors stay in registers across windows; one that a group
           // advances (a long visit) is stored before and reloaded after
@@ -477,64 +495,74 @@ __global__ __launch_bounds__(W_NT) void k_c4_window(C4Args A) {
                 rdesc[j] = D[sg];
                 stale &= ~(1u << j);
               }
-              if (rdesc[j].z < hi) {
-                if (rdesc[j].w < hi) {
-                  D[sg] = rdesc[j];
-                  queue[atomicAdd(&s_q, 1)] = sg;
-                  stale |= 1u << j;
-                } else {
-                  wedges += short_visit(A, ncol4, cnt, rdesc[j], wlo, hi);
-                }
+              if (rdesc[j].z < hi && rdesc[j].w < hi) {
+                D[sg] = rdesc[j];
+                queue[atomicAdd(&s_q, 1)] = sg;
+                stale |= 1u << j;
+              } else {
+                if (rdesc[j].z < hi)
+                  wedges += short_visit(A, ncol4, cnt, rdesc[j], wlo, hi, acc);
+                zmin = min(zmin, rdesc[j].z);
               }
             }
           }
         } else {
           for (int sg = s0 + tid; sg < s1; sg += W_NT) {
             int4 d = D[sg];
-            if (d.z >= hi) continue;  // nothing in this window
-            if (d.w < hi) {           // 8 entries or more: queue it
+            if (d.z < hi && d.w < hi) {  // 8 entries or more: queue it
               queue[atomicAdd(&s_q, 1)] = sg;
               continue;
             }
-            wedges += short_visit(A, ncol4, cnt, d, wlo, hi);
-            D[sg] = d;
+            if (d.z < hi) {
+              wedges += short_visit(A, ncol4, cnt, d, wlo, hi, acc);
+              D[sg] = d;
+            }
+            zmin = min(zmin, d.z);
           }
         }
+        if (zmin != INT_MAX) atomicMin(&s_minz, zmin);
         __syncthreads();
-        // ---- queued long segments, one 8-lane group each: step k reads the
-        // 64 entries [base + 64k, base + 64k + 64); lane gl holds entries
-        // 4 gl .. 4 gl + 3 and 32 + 4 gl .. 32 + 4 gl + 3 of the step
+        // ---- queued long segments, one 8-lane group each: a step reads the
+        // STEP entries [p, p + STEP); lane gl holds entries
+        // 4 (W_GL k + gl) + r (k < W_LD, r < 4) of the step
         const int nq = s_q;
         int qi = g;
-        int4 dA = qi < nq ? D[queue[qi]] : make_int4(0, 0, INT_MAX, INT_MAX);
-        int64_t pA = (int64_t)dA.x & ~int64_t(63);  // first step, aligned to 64 entries
-        int4 a0 = qi < nq ? ncol4[(pA >> 2) + gl] : make_int4(0, 0, 0, 0);
-        int4 a1 = qi < nq ? ncol4[(pA >> 2) + 8 + gl] : make_int4(0, 0, 0, 0);
+        int4 dA = qi < nq ? D[queue[qi]] : kNone;
+        int64_t pA = (int64_t)dA.x & ~int64_t(STEP - 1);
+        int4 a[W_LD];
+#pragma unroll
+        for (int k = 0; k < W_LD; k++)
+          a[k] = qi < nq ? ncol4[(pA >> 2) + W_GL * k + gl] : make_int4(0, 0, 0, 0);
         while (qi < nq) {  // uniform in the group
           const int sg = queue[qi];
           const int qn = qi + W_NG;
-          const int4 dB = qn < nq ? D[queue[qn]] : make_int4(0, 0, INT_MAX, INT_MAX);
-          const int64_t pB = (int64_t)dB.x & ~int64_t(63);
-          int4 b0v = qn < nq ? ncol4[(pB >> 2) + gl] : make_int4(0, 0, 0, 0);
-          int4 b1v = qn < nq ? ncol4[(pB >> 2) + 8 + gl] : make_int4(0, 0, 0, 0);
+          const int4 dB = qn < nq ? D[queue[qn]] : kNone;
+          const int64_t pB = (int64_t)dB.x & ~int64_t(STEP - 1);
+          int4 bn[W_LD];
+#pragma unroll
+          for (int k = 0; k < W_LD; k++)
+            bn[k] = qn < nq ? ncol4[(pB >> 2) + W_GL * k + gl] : make_int4(0, 0, 0, 0);
           const int64_t c0 = dA.x, e = dA.y;
           int64_t p = pA;
           int64_t cend = c0;  // new cursor
           for (;;) {
-            // the 8 entries of this lane in this step
-            int32_t xs[8];
-            xs[0] = a0.x; xs[1] = a0.y; xs[2] = a0.z; xs[3] = a0.w;
-            xs[4] = a1.x; xs[5] = a1.y; xs[6] = a1.z; xs[7] = a1.w;
             int mine = 0;
+            uint64_t part = 0;  // < 4 W_LD counts of < 2^32 each
+            // the step's entries from the cursor on and before the row end
+            const int lo_o = (int)(c0 > p ? c0 - p : 0);
+            const int hi_o = (int)(e - p < STEP ? e - p : STEP);
 #pragma unroll
-            for (int r = 0; r < 8; r++) {
-              const int64_t idx = p + (r < 4 ? 4 * gl + r : 32 + 4 * gl + (r - 4));
-              const bool in = idx >= c0 && idx < e && xs[r] < hi;
-              if (in) {
-                window_inc(A, cnt, wlo, xs[r]);
-                mine++;
+            for (int k = 0; k < W_LD; k++)
+#pragma unroll
+              for (int r = 0; r < 4; r++) {
+                const int32_t xv = comp(a[k], r);
+                const int o = 4 * (W_GL * k + gl) + r;
+                if (o >= lo_o && o < hi_o && xv < hi) {
+                  part += window_inc(A, cnt, wlo, xv);
+                  mine++;
+                }
               }
-            }
+            acc += part;
             wedges += (unsigned long long)mine;
             // entries in the window form a run from the cursor: its length is
             // the group's total
@@ -543,23 +571,31 @@ __global__ __launch_bounds__(W_NT) void k_c4_window(C4Args A) {
             for (int o = 1; o < W_GL; o <<= 1) tot += __shfl_xor(tot, o, WAVE);
             const int64_t first = p > c0 ? p : c0;
             cend = first + tot;
-            if (cend < p + 64 || p + 64 >= e) break;  // the run ends in this step
-            p += 64;
-            a0 = ncol4[(p >> 2) + gl];
-            a1 = ncol4[(p >> 2) + 8 + gl];
+            if (cend < p + STEP || p + STEP >= e) break;  // the run ends in this step
+            p += STEP;
+#pragma unroll
+            for (int k = 0; k < W_LD; k++) a[k] = ncol4[(p >> 2) + W_GL * k + gl];
           }
-          if (gl == 0)
-            D[sg] = make_int4((int)cend, (int)e, row_at(A.ncol, cend, e), row_at(A.ncol, cend + 7, e));
+          if (gl == 0) {
+            const int32_t vnext = row_at(A.ncol, cend, e);
+            D[sg] = make_int4((int)cend, (int)e, vnext, row_at(A.ncol, cend + 7, e));
+            atomicMin(&s_minz, vnext);
+          }
           qi = qn;
           dA = dB;
           pA = pB;
-          a0 = b0v;
-          a1 = b1v;
+#pragma unroll
+          for (int k = 0; k < W_LD; k++) a[k] = bn[k];
         }
         __syncthreads();
       }
-      window_close(A, cnt, wlo, (int)(uwords - wlo < WORDS ? uwords - wlo : WORDS), acc);
+      // clear the counters; the next window starts at the word of the
+      // smallest value a cursor points at
+      const int32_t minz = s_minz;
+      const int used = uwords - wlo < WORDS ? uwords - wlo : WORDS;
+      for (int i = tid; i < used; i += W_NT) cnt[i] = 0;
       __syncthreads();
+      wlo = minz >= u ? uwords : zone_word(A, minz);
     }
   }
   block_add_u128<W_NT>(&A.scal->acc[ACC_C4], acc);
@@ -594,19 +630,20 @@ void c4_run(const Prep& P, const Classes& C, Scal* scal, const Tuning& tu, uint3
     throw Fail(M4_EINTERNAL, "workspace too small (c4)");
   fill_u32(&scal->work[0], 0, 8, s);
   const int light = tu.c4_light_max;
+  const int med = std::max(tu.c4_med_max, light);  // empty medium bucket when <= light
   // rows by degree: <= 64 with 8 lanes, <= 4096 with a wavefront, longer
   // rows with a workgroup
   const int64_t b64 = C.bound[4], b4096 = C.bound[7];
   if (kt) kt->begin(M4_K_C4_PLAN, s);
   if (b64 > 0)
     k_c4_plan<8><<<blocks_for(b64 * 8, 256), 256, 0, s>>>(P.nptr, P.ncol, P.dr, P.dlo, 0, b64,
-                                                          C.r1, light, wub, key, P.own_lo, P.hi());
+                                                          C.r1, light, med, wub, key, P.own_lo, P.hi());
   if (b4096 > b64)
     k_c4_plan<64><<<blocks_for((b4096 - b64) * 64, 256), 256, 0, s>>>(
-        P.nptr, P.ncol, P.dr, P.dlo, b64, b4096, C.r1, light, wub, key, P.own_lo, P.hi());
+        P.nptr, P.ncol, P.dr, P.dlo, b64, b4096, C.r1, light, med, wub, key, P.own_lo, P.hi());
   if (n > b4096)
     k_c4_plan_big<<<(unsigned)(n - b4096), 1024, 0, s>>>(P.nptr, P.ncol, P.dr, P.dlo, b4096, C.r1,
-                                                         light, wub, key, P.own_lo, P.hi());
+                                                         light, med, wub, key, P.own_lo, P.hi());
   radix_pass(key, nullptr, n, 0, 2, nullptr, order, rtmp, start, s);
   k_zone_bounds<<<1, 64, 0, s>>>(P.dr, n, start + CB_N + 1);
   int64_t hstart[CB_N + 3];
@@ -616,7 +653,7 @@ void c4_run(const Prep& P, const Classes& C, Scal* scal, const Tuning& tu, uint3
   const int64_t z1 = std::max<int64_t>(hstart[CB_N + 1], C.r1);
   const int64_t z2 = std::max<int64_t>(hstart[CB_N + 2], z1);
   const int64_t aw = (z1 - C.r1 + 7) >> 3, bw = (z2 - z1 + 3) >> 2;
-  const int64_t H = hstart[CB_WIN32 + 1] - hstart[CB_WIN16];
+  const int64_t H = hstart[CB_WIN + 1] - hstart[CB_WIN];
   int4* desc = nullptr;
   if (H > 0) {
     k_c4_heavy_len<<<blocks_for(H, 256), 256, 0, s>>>(order, start, P.dlo, hlen);
@@ -648,25 +685,34 @@ void c4_run(const Prep& P, const Classes& C, Scal* scal, const Tuning& tu, uint3
   A.flags = flags;
   A.seg_off = seg_off;
   A.desc = desc;
-  A.z1 = z1;
-  A.z2 = z2;
-  A.aw = aw;
-  A.bw = bw;
+  A.z1 = (int32_t)z1;
+  A.z2 = (int32_t)z2;
+  A.aw = (int32_t)aw;
+  A.bw = (int32_t)bw;
+  A.zr1 = (int32_t)C.r1;
   // heavy owners first: one 1024-thread workgroup per CU
-  if (hstart[CB_WIN16 + 1] > hstart[CB_WIN16]) {
-    A.bucket = CB_WIN16;
-    A.slot = M4_K_C4_WIN16;
-    A.work = &scal->work[CB_WIN16];
-    if (kt) kt->begin(M4_K_C4_WIN16, s);
+  if (hstart[CB_WIN + 1] > hstart[CB_WIN]) {
+    A.bucket = CB_WIN;
+    A.slot = M4_K_C4_WINDOW;
+    A.work = &scal->work[CB_WIN];
+    if (kt) kt->begin(M4_K_C4_WINDOW, s);
     k_c4_window<<<(unsigned)num_cu, W_NT, 0, s>>>(A);
-    if (kt) kt->end(M4_K_C4_WIN16, s);
+    if (kt) kt->end(M4_K_C4_WINDOW, s);
+  }
+  if (hstart[CB_MED + 1] > hstart[CB_MED]) {
+    A.bucket = CB_MED;
+    A.slot = M4_K_C4_MED;
+    A.work = &scal->work[CB_MED];
+    if (kt) kt->begin(M4_K_C4_MED, s);
+    k_c4_hash<1024, C4_MED_SLOTS, 4><<<(unsigned)num_cu, 1024, 0, s>>>(A);
+    if (kt) kt->end(M4_K_C4_MED, s);
   }
   if (hstart[CB_HASH + 1] > hstart[CB_HASH]) {
     A.bucket = CB_HASH;
     A.slot = M4_K_C4_HASH;
     A.work = &scal->work[CB_HASH];
     if (kt) kt->begin(M4_K_C4_HASH, s);
-    k_c4_hash<<<(unsigned)(num_cu * 4), H_NT, 0, s>>>(A);
+    k_c4_hash<256, C4_HASH_SLOTS, 4><<<(unsigned)(num_cu * 4), 256, 0, s>>>(A);
     if (kt) kt->end(M4_K_C4_HASH, s);
   }
 }

@@ -28,16 +28,17 @@ enum Stat { ST_STEPS = 0, ST_WEDGES, ST_LOOKUPS, ST_HITS, ST_N = 8 };
 // Triangle-owner buckets by out-degree k = d+(u).
 enum TriBucket { TB_NONE = 0, TB_WAVE, TB_LDS, TB_GLOBAL, TB_N = 4 };
 // 4-cycle-owner buckets by wedge bound.
-enum C4Bucket { CB_NONE = 0, CB_HASH, CB_WIN16, CB_WIN32, CB_N = 4 };
+enum C4Bucket { CB_NONE = 0, CB_HASH, CB_MED, CB_WIN, CB_N = 4 };
 
 // Largest out-degree handled with the bitmap rows in LDS.
 constexpr int TRI_LDS_MAX = 1024;
 // 4-cycle window: 32768 words (128 KiB of LDS) of zoned counters.
 constexpr int C4_WIN_WORDS = 32768;
-constexpr int C4_HASH_SLOTS = 4096;
+constexpr int C4_HASH_SLOTS = 4096;   // light owners: 256 threads, load <= 1/2
+constexpr int C4_MED_SLOTS = 16384;   // medium owners: 1024 threads, load <= 3/4
 // Entries of slack after the last row of a rank-space CSR, so that 16-byte
 // vector loads aligned below a cursor may run past the end of the array.
-constexpr int NCOL_PAD = 64;
+constexpr int NCOL_PAD = 256;
 
 struct Scal {
   U128 acc[ACC_N + 1];
@@ -99,6 +100,7 @@ struct Arena {
 struct Tuning {
   int tri_wave_max = 64;    // <= WAVE
   int c4_light_max = 2048;  // wedge bound for the hash bucket
+  int c4_med_max = 12288;   // wedge bound for the medium hash bucket (0: none)
   int grid_mult = 8;        // persistent blocks per CU for light kernels
   int batch_variant = 0;    // batched kernel: 0 = 1024 threads / 96 KiB, 1 = 512 / 40 KiB
   int batch_light = 128;    // batched kernel: wedge bound of the wavefront hash

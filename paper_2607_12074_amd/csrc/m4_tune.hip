@@ -34,6 +34,7 @@ void to_public(const Tuning& t, m4_tuning* out) {
   out->batch_variant = t.batch_variant;
   out->batch_light = t.batch_light;
   out->hub_min = t.hub_min;
+  out->c4_med_max = t.c4_med_max;
 }
 
 }  // namespace
@@ -49,13 +50,15 @@ extern "C" int m4_set_tuning(m4_ctx* ctx, const m4_tuning* t) {
   if (t->tri_wave_max < 2 || t->tri_wave_max > 64 || t->c4_light_max < 1 ||
       t->c4_light_max > C4_HASH_SLOTS / 2 || (t->batch_variant != 0 && t->batch_variant != 1) ||
       t->batch_light < 1 || t->batch_light > 256 ||
-      (t->hub_min != 0 && (t->hub_min < 4 || t->hub_min > 65536)))
+      (t->hub_min != 0 && (t->hub_min < 4 || t->hub_min > 65536)) || t->c4_med_max < 0 ||
+      t->c4_med_max > 3 * C4_MED_SLOTS / 4)
     return set_error(ctx, M4_EINVAL, "tuning value out of range");
   ctx->tune.tri_wave_max = t->tri_wave_max;
   ctx->tune.c4_light_max = t->c4_light_max;
   ctx->tune.batch_variant = t->batch_variant;
   ctx->tune.batch_light = t->batch_light;
   ctx->tune.hub_min = t->hub_min;
+  ctx->tune.c4_med_max = t->c4_med_max;
   return M4_OK;
 }
 
@@ -67,65 +70,78 @@ extern "C" int m4_autotune(m4_ctx* ctx, const m4_csr* graph, const m4_batch* bat
   Tuning best = start;
   try {
     if (graph) {
-      const int waves[] = {16, 32, 64};
-      const int lights[] = {256, 512, 1024, 2048};
+      // one candidate: a warm run, then the best of reps timed runs; every
+      // candidate must reproduce the first one's counts
       uint64_t ref[6];
       bool have_ref = false;
+      auto time_cfg = [&](const Tuning& t, double* ms) -> int {
+        ctx->tune = t;
+        uint64_t cnt[6];
+        int rc = m4_count_motifs4_ex(ctx, graph, nullptr, cnt, nullptr);
+        if (rc != M4_OK) return rc;
+        if (!have_ref) {
+          memcpy(ref, cnt, sizeof(ref));
+          have_ref = true;
+        } else if (memcmp(ref, cnt, sizeof(ref)) != 0) {
+          return set_error(ctx, M4_EINTERNAL, "autotune: thresholds changed the counts");
+        }
+        *ms = 1e300;
+        for (int r = 0; r < reps; r++) {
+          const double t0 = wall_ms();
+          rc = m4_count_motifs4_ex(ctx, graph, nullptr, cnt, nullptr);
+          if (rc != M4_OK) return rc;
+          *ms = std::min(*ms, wall_ms() - t0);
+        }
+        return M4_OK;
+      };
       double best_ms = 1e300;
+      auto try_cfg = [&](const Tuning& t) -> int {
+        double ms;
+        const int rc = time_cfg(t, &ms);
+        if (rc == M4_OK && ms < best_ms) {
+          best_ms = ms;
+          best = t;
+        }
+        return rc;
+      };
+      // bucket bounds first, then the hub-table threshold, then the medium
+      // 4-cycle bucket, each at the best setting found so far
+      const int waves[] = {16, 32, 64};
+      const int lights[] = {256, 512, 1024, 2048};
       for (int w : waves)
         for (int l : lights) {
-          m4_opts o{};
-          o.tri_wave_max = w;
-          o.c4_light_max = l;
-          uint64_t cnt[6];
-          int rc = m4_count_motifs4_ex(ctx, graph, &o, cnt, nullptr);  // warm
-          if (rc != M4_OK) return rc;
-          if (!have_ref) {
-            memcpy(ref, cnt, sizeof(ref));
-            have_ref = true;
-          } else if (memcmp(ref, cnt, sizeof(ref)) != 0) {
-            return set_error(ctx, M4_EINTERNAL, "autotune: thresholds changed the counts");
-          }
-          double ms = 1e300;
-          for (int r = 0; r < reps; r++) {
-            const double t0 = wall_ms();
-            rc = m4_count_motifs4_ex(ctx, graph, &o, cnt, nullptr);
-            if (rc != M4_OK) return rc;
-            ms = std::min(ms, wall_ms() - t0);
-          }
-          if (ms < best_ms) {
-            best_ms = ms;
-            best.tri_wave_max = w;
-            best.c4_light_max = l;
+          Tuning t = start;
+          t.tri_wave_max = w;
+          t.c4_light_max = l;
+          const int rc = try_cfg(t);
+          if (rc != M4_OK) {
+            ctx->tune = start;
+            return rc;
           }
         }
-      // then the hub-table threshold at the chosen bucket bounds
       const int hub_mins[] = {0, 16, 32, 64, 128};
+      const Tuning after_buckets = best;
       for (int hm : hub_mins) {
-        ctx->tune.hub_min = hm;
-        m4_opts o{};
-        o.tri_wave_max = best.tri_wave_max;
-        o.c4_light_max = best.c4_light_max;
-        uint64_t cnt[6];
-        int rc = m4_count_motifs4_ex(ctx, graph, &o, cnt, nullptr);
-        if (rc == M4_OK && memcmp(ref, cnt, sizeof(ref)) != 0)
-          rc = set_error(ctx, M4_EINTERNAL, "autotune: thresholds changed the counts");
-        double ms = 1e300;
-        for (int r = 0; r < reps && rc == M4_OK; r++) {
-          const double t0 = wall_ms();
-          rc = m4_count_motifs4_ex(ctx, graph, &o, cnt, nullptr);
-          ms = std::min(ms, wall_ms() - t0);
-        }
+        Tuning t = after_buckets;
+        t.hub_min = hm;
+        const int rc = try_cfg(t);
         if (rc != M4_OK) {
           ctx->tune = start;
           return rc;
         }
-        if (ms < best_ms) {
-          best_ms = ms;
-          best.hub_min = hm;
+      }
+      const int meds[] = {0, 6144, 12288};
+      const Tuning after_hubs = best;
+      for (int md : meds) {
+        Tuning t = after_hubs;
+        t.c4_med_max = md;
+        const int rc = try_cfg(t);
+        if (rc != M4_OK) {
+          ctx->tune = start;
+          return rc;
         }
       }
-      ctx->tune.hub_min = start.hub_min;
+      ctx->tune = start;
     }
     if (batch) {
       const int64_t G = batch->num_graphs;

@@ -147,6 +147,10 @@ def test_threshold_sweep_identical(ctx):
     for tw in (2, 5, 16, 64):
         for cl in (1, 64, 2048):
             assert ctx.count(*g, tri_wave_max=tw, c4_light_max=cl) == ref, (tw, cl)
+    # medium 4-cycle bucket: none, below the light bound (empty), partial, full
+    for cl, md in ((64, -1), (2048, 1000), (64, 3000), (1, 12288)):
+        got, st = ctx.count(*g, c4_light_max=cl, c4_med_max=md, stats=True)
+        assert got == ref, (cl, md)
 
 
 def test_device_tensor_input(ctx):
