@@ -48,7 +48,7 @@ KERNEL_SYMBOL = {
     "tri_128": "k_tri_lds<128, 256>", "tri_wave": "k_tri_lds<64, 64>",
     "c4_window": "k_c4_window", "c4_med": "k_c4_hash<1024, 16384, 4>",
     "c4_hash": "k_c4_hash<256, 4096, 4>", "closure": "k_closure", "c4_plan": "k_c4_plan",
-    "build": "(CSR builder kernels)",
+    "build": "(CSR builder kernels)", "tri_hubs": "k_hub_insert",
 }
 
 
@@ -85,6 +85,81 @@ def traffic_for(kernel: str, digest: str):
     if not ent or rec.get("source_digest") != digest:
         return None
     return ent.get("bytes_per_launch")
+
+
+def short_kernel_name(full: str) -> str:
+    """'void m4::(anonymous namespace)::k_x<1, 2>(args)' -> 'k_x<1, 2>'."""
+    s = full[5:] if full.startswith("void ") else full
+    for pre in ("m4::(anonymous namespace)::", "m4::"):
+        if s.startswith(pre):
+            s = s[len(pre):]
+    depth = 0
+    for i, ch in enumerate(s):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            return s[:i]
+    return s
+
+
+def report_stats(path: str, top: int = 24) -> str:
+    """Markdown table of a rocprofv3 --stats kernel summary (CSV)."""
+    import csv
+    rows = list(csv.DictReader(open(path)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    out = ["| kernel | calls | avg us | min us | max us | share % |", "|---|---|---|---|---|---|"]
+    for r in rows[:top]:
+        out.append(f"| `{short_kernel_name(r['Name'])}` | {r['Calls']} | "
+                   f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
+                   f"{float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |")
+    return "\n".join(out)
+
+
+def report_traffic(fetch_csv: str, write_csv: str, out_json: str) -> str:
+    """HBM bytes per launch from two rocprofv3 --pmc runs (FETCH_SIZE, then
+    WRITE_SIZE, KiB per dispatch) of `bench.py --copy-calib`, each scaled by
+    the counter's reading for the 1 GiB device copy of that run; writes the
+    record that traffic_for() reads and returns a markdown table."""
+    import csv
+    from collections import defaultdict
+
+    def per_kernel(path, counter):
+        vals = defaultdict(list)
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] == counter:
+                vals[short_kernel_name(r["Kernel_Name"])].append(float(r["Counter_Value"]))
+        return vals
+
+    f, w = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
+    copy_kib = 1 << 20  # the calibration copy moves 1 GiB each way
+    cf = [v for v in f.get("__amd_rocclr_copyBuffer", []) if v > copy_kib / 8]
+    cw = [v for v in w.get("__amd_rocclr_copyBuffer", []) if v > copy_kib / 8]
+    if not cf or not cw:
+        raise SystemExit("no 1 GiB calibration copy in the PMC runs (run with --copy-calib)")
+    ff, wf = copy_kib / (sum(cf) / len(cf)), copy_kib / (sum(cw) / len(cw))
+    kernels = {}
+    for k in sorted(set(f) & set(w)):
+        if k == "__amd_rocclr_copyBuffer":
+            continue
+        fk, wk = sum(f[k]) / len(f[k]), sum(w[k]) / len(w[k])
+        kernels[k] = {"dispatches": len(f[k]), "fetch_kib": fk, "write_kib": wk,
+                      "bytes_per_launch": 1024.0 * (fk * ff + wk * wf)}
+    rec = {"source_digest": source_digest(),
+           "calibration": {"copy_bytes": 1 << 30, "fetch_factor": ff, "write_factor": wf},
+           "kernels": kernels}
+    with open(out_json, "w") as fh:
+        json.dump(rec, fh, indent=1, sort_keys=True)
+        fh.write("\n")
+    out = [f"Calibration: a 1 GiB device copy reads FETCH_SIZE x {ff:.3f} and "
+           f"WRITE_SIZE x {wf:.3f} of its true bytes; source digest {rec['source_digest']}.", "",
+           "| kernel | dispatches | FETCH KiB | WRITE KiB | HBM bytes / launch (scaled) |",
+           "|---|---|---|---|---|"]
+    for k, e in sorted(kernels.items(), key=lambda kv: -kv[1]["bytes_per_launch"])[:16]:
+        out.append(f"| `{k}` | {e['dispatches']} | {e['fetch_kib']:.0f} | {e['write_kib']:.0f} | "
+                   f"{e['bytes_per_launch']:.4g} |")
+    return "\n".join(out)
 
 
 def run_batch_leg(ctx, args):
@@ -229,7 +304,17 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=32.0)
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (PMC calibration)")
+    ap.add_argument("--report-stats", metavar="CSV",
+                    help="print a markdown table of a rocprofv3 kernel-stats CSV and exit")
+    ap.add_argument("--report-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic.json from two PMC runs and exit")
     args = ap.parse_args()
+    if args.report_stats:
+        print(report_stats(args.report_stats))
+        return
+    if args.report_traffic:
+        print(report_traffic(*args.report_traffic, os.path.join(ROOT, "profiles", "traffic.json")))
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on exactly one GPU (--gpus 1); "
               f"--gpus {args.gpus} is not supported", file=sys.stderr)
