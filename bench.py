@@ -302,6 +302,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=600,
                     help="requests of the serving leg (0 = skip it)")
     ap.add_argument("--serve-budget-gb", type=float, default=32.0)
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the library's default single-graph thresholds")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (PMC calibration)")
     ap.add_argument("--report-stats", metavar="CSV",
@@ -332,6 +334,19 @@ def main():
     col_d = torch.from_numpy(col).to(dev)
     torch.cuda.synchronize()
     ctx = m4.Context(0)
+
+    # single-graph thresholds picked by the autotuner on a smaller graph of
+    # the same family (scale - 2, another seed), outside the timed region
+    graph_tuning = None
+    if not args.no_tune:
+        import graphgen as gg
+        srp, scol = gg.rmat(max(args.scale - 2, 8), args.edge_factor, 0.57, 0.19, 0.19,
+                            args.seed + 100, True)
+        sample = (torch.from_numpy(srp).to(dev), torch.from_numpy(scol).to(dev))
+        t0 = time.perf_counter()
+        graph_tuning = ctx.autotune(graph=sample, reps=3)
+        graph_tuning["tune_s"] = round(time.perf_counter() - t0, 2)
+        note(f"single-graph tuning {graph_tuning}")
 
     if args.copy_calib:
         a = torch.empty(1 << 28, dtype=torch.int32, device=dev)
@@ -409,7 +424,8 @@ def main():
         "config": {"workload": f"rmat-social scale {args.scale} edge-factor "
                                f"{args.edge_factor} (a,b,c,d)=(0.57,0.19,0.19,0.05) "
                                f"seed {args.seed}, symmetrised and deduplicated",
-                   "n": n, "m": m, "parallelism": "single-gpu"},
+                   "n": n, "m": m, "parallelism": "single-gpu",
+                   "tuning": graph_tuning},
         "counts": list(counts),
         "parity_vs_oracle": parity,
         "roofline": {"bound": "hbm", "kernel": KERNEL_SYMBOL[dname], "achieved": achieved,

@@ -168,7 +168,7 @@ int m4_edge_triangles(m4_ctx* ctx, const m4_csr* g, const m4_opts* opts,
  * context's tuning is unchanged. */
 typedef struct {
   int32_t tri_wave_max;  /* single graph: owners with out-degree <= this use one
-                            64-thread workgroup (2..64, default 64)            */
+                            64-thread workgroup (2..64, default 32)            */
   int32_t c4_light_max;  /* single graph: owners with wedge bound <= this use the
                             LDS hash (1..2048, default 2048)                   */
   int32_t batch_variant; /* fused batched kernel: 0 = 1024 threads with 96 KiB of
@@ -183,9 +183,19 @@ typedef struct {
                             else 4..65536, default 32)                        */
   int32_t c4_med_max;    /* single graph: owners with wedge bound in
                             (c4_light_max, c4_med_max] use the 16384-slot LDS
-                            hash, heavier ones the counter windows (0 = none,
-                            else up to 12288, default 12288)                 */
-  int32_t reserved[2];
+                            hash in one pass, heavier ones the counter windows
+                            (0 = no medium bucket, else up to 12288, default
+                            6144)                                             */
+  int32_t probe_w;       /* single graph: a triangle row is probed in the hub
+                            table when probe_w * (probes) < 3 * (elements a
+                            scan would read) (1..256, default 4)              */
+  int32_t c4_med_win;    /* single graph: an owner with wedge bound in
+                            (12288, 65536] also uses the medium table, one
+                            pass per rank range of at most 12288 endpoints,
+                            when 16 * (windows it needs) >= c4_med_win *
+                            ceil(bound / 12288), i.e. its endpoints are thin
+                            over many windows (0 = never, default 64; needs
+                            c4_med_max > 0)                                   */
 } m4_tuning;
 
 int m4_get_tuning(const m4_ctx* ctx, m4_tuning* out);

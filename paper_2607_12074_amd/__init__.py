@@ -78,10 +78,10 @@ class Tuning(ctypes.Structure):
     _fields_ = [("tri_wave_max", ctypes.c_int32), ("c4_light_max", ctypes.c_int32),
                 ("batch_variant", ctypes.c_int32), ("batch_light", ctypes.c_int32),
                 ("hub_min", ctypes.c_int32), ("c4_med_max", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("probe_w", ctypes.c_int32), ("c4_med_win", ctypes.c_int32)]
 
     def to_dict(self):
-        return {f: int(getattr(self, f)) for f, _ in self._fields_[:6]}
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
 class Result(ctypes.Structure):

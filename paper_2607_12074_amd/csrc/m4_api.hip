@@ -204,8 +204,8 @@ Tuning tuning_for(const m4_ctx* c, const m4_opts* o) {
   if (o && o->tri_wave_max > 0) tu.tri_wave_max = o->tri_wave_max;
   if (o && o->c4_light_max > 0) tu.c4_light_max = o->c4_light_max;
   if (o && o->c4_med_max != 0) tu.c4_med_max = o->c4_med_max < 0 ? 0 : o->c4_med_max;
-  // the hash tables hold C4_HASH_SLOTS keys at load <= 1/2 and C4_MED_SLOTS
-  // keys at load <= 3/4
+  // the light table holds C4_HASH_SLOTS keys at load <= 1/2, the medium one
+  // C4_MED_SLOTS keys at load <= 3/4 in one pass
   tu.c4_light_max = std::max(0, std::min(tu.c4_light_max, C4_HASH_SLOTS / 2));
   tu.c4_med_max = std::max(0, std::min(tu.c4_med_max, 3 * C4_MED_SLOTS / 4));
   return tu;
@@ -346,7 +346,8 @@ extern "C" int m4_count_motifs4_ex(m4_ctx* ctx, const m4_csr* g, const m4_opts* 
   M4_HIP(hipMemcpyAsync(ctx->scal_host, ctx->scal, sizeof(Scal), hipMemcpyDeviceToHost, s));
   M4_HIP(hipStreamSynchronize(s));
   const Scal& h = *ctx->scal_host;
-  if (h.err) return set_error(ctx, M4_EINVAL, "CSR is not simple, symmetric and sorted");
+  if (h.err & 1) return set_error(ctx, M4_EINVAL, "CSR is not simple, symmetric and sorted");
+  if (h.err) return set_error(ctx, M4_EINTERNAL, "4-cycle range plan exceeded its bound");
   if (h.status == 3) return set_error(ctx, M4_EOVERFLOW, "a count is >= 2^64");
   if (h.status != 0) return set_error(ctx, M4_EINTERNAL, "closure consistency check failed");
   for (int i = 0; i < 6; i++) out[i] = h.out[i];

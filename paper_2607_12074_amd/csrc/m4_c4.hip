@@ -60,10 +60,60 @@ struct C4Args {
   int32_t z1, z2, aw, bw, zr1;  // zr1: r1 as a 32-bit rank
 };
 
-// bucket of an owner with wedge bound w > 0
-__device__ __forceinline__ uint32_t c4_bucket(int64_t w, int light_max, int med_max) {
-  if (w <= light_max) return CB_HASH;
-  if (w <= med_max) return CB_MED;
+// first ranks with degree > 15 and > 255 (degrees are sorted by rank)
+__global__ void k_zone_bounds(const int32_t* __restrict__ dr, int64_t n, int64_t* __restrict__ out) {
+  const int i = threadIdx.x;
+  if (i >= 2) return;
+  const int thr = i == 0 ? 15 : 255;
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (dr[mid] <= thr) lo = mid + 1;
+    else hi = mid;
+  }
+  out[i] = lo;
+}
+
+// Multi-pass medium owners (wedge bound above 3/4 of the table) are counted
+// over rank ranges cut from a histogram with bins of 2^hs ranks, 2^hs <=
+// C4_MED_BIN_MAX, so one bin never holds more distinct endpoints than a pass
+// may insert; their rank span must fit C4_MED_SLOTS such bins.  A wedge
+// bound of at most C4_MED_MAX needs at most 12 ranges.
+constexpr int C4_MED_BIN_MAX = 8192;
+constexpr int C4_MED_RANGES = 32;
+constexpr int64_t C4_MED_SPAN = (int64_t)C4_MED_SLOTS * C4_MED_BIN_MAX;
+constexpr int64_t C4_MED_CAP = 3 * C4_MED_SLOTS / 4;
+
+// Windows of dense counters owner u needs over ranks [r1, u); zb holds the
+// first ranks of degree > 15 and > 255 (the zone bounds).
+__device__ __forceinline__ int64_t c4_windows(const int64_t* zb, int64_t r1, int64_t u) {
+  const int64_t z1 = zb[0] > r1 ? zb[0] : r1, z2 = zb[1] > z1 ? zb[1] : z1;
+  const int64_t aw = (z1 - r1 + 7) >> 3, bw = (z2 - z1 + 3) >> 2;
+  int64_t words;
+  if (u <= r1) words = 0;
+  else if (u <= z1) words = (u - r1 + 7) >> 3;
+  else if (u <= z2) words = aw + ((u - z1 + 3) >> 2);
+  else words = aw + bw + (u - z2);
+  return (words + C4_WIN_WORDS - 1) / C4_WIN_WORDS;
+}
+
+// Bucket of owner u with wedge bound w > 0.  A table pass costs about one
+// read of every wedge endpoint and a window costs a pass over the owner's
+// lower neighbours, so an owner above the single-pass bound goes to the
+// ranged table only when its endpoints are thin over many windows:
+// 16 windows >= med_win ranges (med_win 0: never).
+struct C4Plan {
+  int light_max, med_max, med_win;
+  const int64_t* zb;
+  int64_t r1;
+};
+__device__ __forceinline__ uint32_t c4_bucket(const C4Plan& pl, int64_t w, int64_t u) {
+  if (w <= pl.light_max) return CB_HASH;
+  if (pl.med_max <= 0) return CB_WIN;
+  if (w <= pl.med_max && w <= C4_MED_CAP) return CB_MED;
+  if (pl.med_win > 0 && w <= C4_MED_MAX && u - pl.r1 < C4_MED_SPAN &&
+      16 * c4_windows(pl.zb, pl.r1, u) >= (int64_t)pl.med_win * ((w + C4_MED_CAP - 1) / C4_MED_CAP))
+    return CB_MED;
   return CB_WIN;
 }
 
@@ -73,8 +123,8 @@ __global__ __launch_bounds__(256) void k_c4_plan(const int64_t* __restrict__ npt
                                                  const int32_t* __restrict__ ncol,
                                                  const int32_t* __restrict__ dr,
                                                  const int32_t* __restrict__ dlo, int64_t r_lo,
-                                                 int64_t r_hi, int64_t r1, int light_max,
-                                                 int med_max, int64_t* __restrict__ wub,
+                                                 int64_t r_hi, int64_t r1, C4Plan pl,
+                                                 int64_t* __restrict__ wub,
                                                  uint32_t* __restrict__ key, int64_t own_lo,
                                                  int64_t own_hi) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -99,7 +149,7 @@ __global__ __launch_bounds__(256) void k_c4_plan(const int64_t* __restrict__ npt
   if (ok && j == 0) {
     wub[u] = s;
     uint32_t k = CB_NONE;
-    if (u >= r1 && nl >= 2 && s > 0) k = c4_bucket(s, light_max, med_max);
+    if (u >= r1 && nl >= 2 && s > 0) k = c4_bucket(pl, s, u);
     key[u] = k;
   }
 }
@@ -109,7 +159,7 @@ __global__ __launch_bounds__(1024) void k_c4_plan_big(const int64_t* __restrict_
                                                       const int32_t* __restrict__ ncol,
                                                       const int32_t* __restrict__ dr,
                                                       const int32_t* __restrict__ dlo, int64_t r_lo,
-                                                      int64_t r1, int light_max, int med_max,
+                                                      int64_t r1, C4Plan pl,
                                                       int64_t* __restrict__ wub,
                                                       uint32_t* __restrict__ key, int64_t own_lo,
                                                       int64_t own_hi) {
@@ -127,27 +177,77 @@ __global__ __launch_bounds__(1024) void k_c4_plan_big(const int64_t* __restrict_
   if (threadIdx.x == 0) {
     wub[u] = tot;
     uint32_t k = CB_NONE;
-    if (u >= r1 && nl >= 2 && tot > 0) k = c4_bucket(tot, light_max, med_max);
+    if (u >= r1 && nl >= 2 && tot > 0) k = c4_bucket(pl, tot, u);
     key[u] = k;
   }
 }
 
 // --------------------------------------------------------- hash buckets
-// One owner at a time per workgroup: the wedge endpoints of the chunk of NT
-// lower neighbours are flattened (a scan of the row lengths), every thread
-// takes UNR endpoints per round with their loads in flight together, and
-// counts them in an open-addressing table in LDS (linear probing, keys
-// inserted with compare-and-swap).  The table is sized to a power of two of
-// at least twice the wedge bound (capped at SLOTS): the number of distinct
-// endpoints never exceeds the wedge bound, which the planner keeps below
-// SLOTS, so a probe always ends.
+// Streams the wedge endpoints x in [r1, u) of owner u to fn: the rows of the
+// lower neighbours, NT at a time, are flattened by a scan of their lengths;
+// every thread takes UNR endpoints per round with their loads in flight
+// together.  Called by every thread of the workgroup.
+template <int NT, int UNR, class F>
+__device__ __forceinline__ void c4_endpoints(const C4Args& A, int32_t u, int nl, int64_t base,
+                                             int32_t* sst, int32_t* spref,
+                                             unsigned long long& reads, F&& fn) {
+  const int tid = threadIdx.x;
+  for (int c0 = 0; c0 < nl; c0 += NT) {
+    const int nc = nl - c0 < NT ? nl - c0 : NT;
+    int len = 0;
+    if (tid < nc) {
+      const int32_t v = A.ncol[base + c0 + tid];
+      sst[tid] = (int32_t)A.nptr[v];
+      len = A.row_len ? A.row_len[v] : A.dr[v];
+    }
+    int64_t tot;
+    const int64_t ex = block_excl_scan64<NT>(len, &tot);
+    if (tid < nc) spref[tid] = (int32_t)ex;
+    if (tid == 0) spref[nc] = (int32_t)tot;
+    __syncthreads();
+    const int total = (int)tot;
+    if (tid == 0) reads += (unsigned long long)total;
+    for (int q0 = 0; q0 < total; q0 += NT * UNR) {
+      int32_t w[UNR];
+#pragma unroll
+      for (int j = 0; j < UNR; j++) {
+        const int q = q0 + j * NT + tid;
+        w[j] = INT_MAX;
+        if (q < total) {
+          const int si = upper_index(spref, nc, q);
+          w[j] = A.ncol[sst[si] + (q - spref[si])];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < UNR; j++)
+        if (w[j] >= A.r1 && w[j] < u) fn(w[j]);
+    }
+    __syncthreads();
+  }
+}
+
+// One owner at a time per workgroup, counting in an open-addressing table in
+// LDS (linear probing, keys inserted with compare-and-swap).  The table is
+// sized to a power of two of at least twice the wedge bound, capped at
+// SLOTS; the number of distinct endpoints never exceeds the wedge bound, so
+// while that bound is at most 3/4 of SLOTS a probe always ends.  Owners of
+// the medium bucket with a larger bound (1024 threads only) are counted in
+// rank ranges: a first pass histograms their endpoints over bins of ranks,
+// the bins are cut greedily into ranges of at most 3/4 SLOTS endpoints (or
+// one bin, which holds at most C4_MED_BIN_MAX distinct ranks), and every
+// range is one pass over the rows that inserts only its own endpoints.  Each
+// endpoint lies in exactly one range, so every c_u[w] is complete in its
+// pass.
 template <int NT, int SLOTS, int UNR>
 __global__ __launch_bounds__(NT) void k_c4_hash(C4Args A) {
   __shared__ int32_t hkey[SLOTS];
   __shared__ uint32_t hcnt[SLOTS];
   __shared__ int32_t sst[NT];
   __shared__ int32_t spref[NT + 1];
-  __shared__ int s_item;
+  __shared__ int32_t s_rng[C4_MED_RANGES + 1];
+  __shared__ int s_item, s_nr;
+  __shared__ uint32_t s_tot;
+  constexpr uint32_t CAP = 3 * SLOTS / 4;
   const int tid = threadIdx.x;
   const int64_t b0 = A.start[A.bucket], cnt = A.start[A.bucket + 1] - b0;
   u128_t acc = 0;
@@ -171,7 +271,7 @@ __global__ __launch_bounds__(NT) void k_c4_hash(C4Args A) {
     item++;
     const int nl = A.dlo[u];
     const int64_t base = A.nptr[u];
-    int64_t wb = A.wub[u];
+    const int64_t wb = A.wub[u];
     int S = 64;
     while (S < 2 * wb && S < SLOTS) S <<= 1;
     const uint32_t mask = (uint32_t)S - 1;
@@ -180,53 +280,95 @@ __global__ __launch_bounds__(NT) void k_c4_hash(C4Args A) {
       owners++;
       segs += (unsigned long long)nl;
     }
-    for (int c0 = 0; c0 < nl; c0 += NT) {
-      const int nc = nl - c0 < NT ? nl - c0 : NT;
-      int len = 0;
-      if (tid < nc) {
-        int32_t v = A.ncol[base + c0 + tid];
-        sst[tid] = (int32_t)A.nptr[v];
-        len = A.row_len ? A.row_len[v] : A.dr[v];
+    auto insert = [&](int32_t x) {
+      uint32_t h = ((uint32_t)x * 0x9E3779B1u) >> shift;
+      for (;;) {
+        const int32_t k = hkey[h];
+        if (k == x) break;
+        if (k == -1) {
+          const int32_t prev = atomicCAS(&hkey[h], -1, x);
+          if (prev == -1 || prev == x) break;
+        }
+        h = (h + 1) & mask;
+      }
+      acc += atomicAdd(&hcnt[h], 1u);
+      wedges++;
+    };
+    if (NT < 1024 || wb <= (int64_t)CAP) {
+      c4_endpoints<NT, UNR>(A, u, nl, base, sst, spref, reads, insert);
+    } else {
+      // histogram of the endpoints over bins of 2^hs ranks (in hcnt)
+      const int32_t span = u - (int32_t)A.r1;
+      int hs = 0;
+      while ((span >> hs) >= SLOTS) hs++;
+      c4_endpoints<NT, UNR>(A, u, nl, base, sst, spref, reads, [&](int32_t x) {
+        atomicAdd(&hcnt[(x - (int32_t)A.r1) >> hs], 1u);
+      });
+      // exclusive prefix of the bins, in place
+      constexpr int PER = SLOTS / NT;
+      uint32_t loc[PER], sum = 0;
+#pragma unroll
+      for (int i = 0; i < PER; i++) {
+        loc[i] = hcnt[tid * PER + i];
+        sum += loc[i];
       }
       int64_t tot;
-      int64_t ex = block_excl_scan64<NT>(len, &tot);
-      if (tid < nc) spref[tid] = (int32_t)ex;
-      if (tid == 0) spref[nc] = (int32_t)tot;
+      uint32_t run = (uint32_t)block_excl_scan64<NT>((int64_t)sum, &tot);
       __syncthreads();
-      const int total = (int)tot;
-      if (tid == 0) reads += (unsigned long long)total;
-      for (int q0 = 0; q0 < total; q0 += NT * UNR) {
-        int32_t w[UNR];
 #pragma unroll
-        for (int j = 0; j < UNR; j++) {
-          const int q = q0 + j * NT + tid;
-          w[j] = INT_MAX;
-          if (q < total) {
-            const int si = upper_index(spref, nc, q);
-            w[j] = A.ncol[sst[si] + (q - spref[si])];
-          }
-        }
-        uint64_t part = 0;
-#pragma unroll
-        for (int j = 0; j < UNR; j++) {
-          const int32_t x = w[j];
-          if (x < A.r1 || x >= u) continue;
-          uint32_t h = ((uint32_t)x * 0x9E3779B1u) >> shift;
-          for (;;) {
-            int32_t k = hkey[h];
-            if (k == x) break;
-            if (k == -1) {
-              int32_t prev = atomicCAS(&hkey[h], -1, x);
-              if (prev == -1 || prev == x) break;
+      for (int i = 0; i < PER; i++) {
+        hcnt[tid * PER + i] = run;
+        run += loc[i];
+      }
+      if (tid == 0) s_tot = (uint32_t)tot;
+      __syncthreads();
+      // greedy ranges: as many bins as fit in CAP endpoints, at least one
+      if (tid == 0) {
+        auto pre = [&](int b) { return b >= SLOTS ? s_tot : hcnt[b]; };
+        int nr = 0, lo = 0;
+        s_rng[0] = (int32_t)A.r1;
+        while (lo < SLOTS && nr < C4_MED_RANGES) {
+          const uint32_t p0 = pre(lo);
+          int l = lo + 1, h = SLOTS;  // largest b in [lo + 1, SLOTS] with pre(b) - p0 <= CAP
+          if (pre(l) - p0 > CAP) {
+            h = l;
+          } else {
+            while (l < h) {
+              const int mid = (l + h + 1) >> 1;
+              if (pre(mid) - p0 <= CAP) l = mid;
+              else h = mid - 1;
             }
-            h = (h + 1) & mask;
+            h = l;
           }
-          part += atomicAdd(&hcnt[h], 1u);
-          wedges++;
+          nr++;
+          const int64_t rk = (int64_t)A.r1 + ((int64_t)h << hs);
+          s_rng[nr] = h >= SLOTS || rk >= u ? u : (int32_t)rk;
+          lo = h;
+          if (s_rng[nr] >= u) break;
         }
-        acc += part;
+        if (s_rng[nr] < u) {  // more ranges than planned for: not counted
+          atomicOr(&A.scal->err, 2);
+          nr = 0;
+        }
+        s_nr = nr;
       }
       __syncthreads();
+      for (int i = tid; i < SLOTS; i += NT) hcnt[i] = 0;
+      __syncthreads();
+      const int nr = s_nr;
+      for (int r = 0; r < nr; r++) {
+        const int32_t lo = s_rng[r], hi = s_rng[r + 1];
+        c4_endpoints<NT, UNR>(A, u, nl, base, sst, spref, reads, [&](int32_t x) {
+          if (x >= lo && x < hi) insert(x);
+        });
+        if (r + 1 < nr) {
+          for (int i = tid; i < S; i += NT) {
+            hkey[i] = -1;
+            hcnt[i] = 0;
+          }
+          __syncthreads();
+        }
+      }
     }
     for (int i = tid; i < S; i += NT) {
       hkey[i] = -1;
@@ -282,20 +424,6 @@ __global__ void k_lowcut(const int64_t* __restrict__ nptr, const int32_t* __rest
   if (v >= n) return;
   const int64_t rend = row_len ? nptr[v] + row_len[v] : nptr[v + 1];
   lowcut[v] = (int32_t)(lower_index(ncol, nptr[v], rend, (int32_t)r1) - nptr[v]);
-}
-
-// first ranks with degree > 15 and > 255 (degrees are sorted by rank)
-__global__ void k_zone_bounds(const int32_t* __restrict__ dr, int64_t n, int64_t* __restrict__ out) {
-  const int i = threadIdx.x;
-  if (i >= 2) return;
-  const int thr = i == 0 ? 15 : 255;
-  int64_t lo = 0, hi = n;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (dr[mid] <= thr) lo = mid + 1;
-    else hi = mid;
-  }
-  out[i] = lo;
 }
 
 __global__ void k_c4_heavy_len(const int32_t* __restrict__ order, const int64_t* __restrict__ start,
@@ -629,23 +757,23 @@ void c4_run(const Prep& P, const Classes& C, Scal* scal, const Tuning& tu, uint3
   if (!wub || !key || !order || !rtmp || !start || !hlen || !seg_off || !stmp || !lowcut)
     throw Fail(M4_EINTERNAL, "workspace too small (c4)");
   fill_u32(&scal->work[0], 0, 8, s);
-  const int light = tu.c4_light_max;
-  const int med = std::max(tu.c4_med_max, light);  // empty medium bucket when <= light
+  // zone bounds first: the planner needs every owner's window count
+  k_zone_bounds<<<1, 64, 0, s>>>(P.dr, n, start + CB_N + 1);
+  C4Plan pl{tu.c4_light_max, tu.c4_med_max, tu.c4_med_win, start + CB_N + 1, C.r1};
   // rows by degree: <= 64 with 8 lanes, <= 4096 with a wavefront, longer
   // rows with a workgroup
   const int64_t b64 = C.bound[4], b4096 = C.bound[7];
   if (kt) kt->begin(M4_K_C4_PLAN, s);
   if (b64 > 0)
     k_c4_plan<8><<<blocks_for(b64 * 8, 256), 256, 0, s>>>(P.nptr, P.ncol, P.dr, P.dlo, 0, b64,
-                                                          C.r1, light, med, wub, key, P.own_lo, P.hi());
+                                                          C.r1, pl, wub, key, P.own_lo, P.hi());
   if (b4096 > b64)
     k_c4_plan<64><<<blocks_for((b4096 - b64) * 64, 256), 256, 0, s>>>(
-        P.nptr, P.ncol, P.dr, P.dlo, b64, b4096, C.r1, light, med, wub, key, P.own_lo, P.hi());
+        P.nptr, P.ncol, P.dr, P.dlo, b64, b4096, C.r1, pl, wub, key, P.own_lo, P.hi());
   if (n > b4096)
     k_c4_plan_big<<<(unsigned)(n - b4096), 1024, 0, s>>>(P.nptr, P.ncol, P.dr, P.dlo, b4096, C.r1,
-                                                         light, med, wub, key, P.own_lo, P.hi());
+                                                         pl, wub, key, P.own_lo, P.hi());
   radix_pass(key, nullptr, n, 0, 2, nullptr, order, rtmp, start, s);
-  k_zone_bounds<<<1, 64, 0, s>>>(P.dr, n, start + CB_N + 1);
   int64_t hstart[CB_N + 3];
   M4_HIP(hipMemcpyAsync(hstart, start, sizeof(hstart), hipMemcpyDeviceToHost, s));
   M4_HIP(hipStreamSynchronize(s));

@@ -36,6 +36,7 @@ constexpr int TRI_LDS_MAX = 1024;
 constexpr int C4_WIN_WORDS = 32768;
 constexpr int C4_HASH_SLOTS = 4096;   // light owners: 256 threads, load <= 1/2
 constexpr int C4_MED_SLOTS = 16384;   // medium owners: 1024 threads, load <= 3/4
+constexpr int C4_MED_MAX = 65536;     // largest wedge bound of the medium bucket
 // Entries of slack after the last row of a rank-space CSR, so that 16-byte
 // vector loads aligned below a cursor may run past the end of the array.
 constexpr int NCOL_PAD = 256;
@@ -98,13 +99,15 @@ struct Arena {
 };
 
 struct Tuning {
-  int tri_wave_max = 64;    // <= WAVE
+  int tri_wave_max = 32;    // <= WAVE
   int c4_light_max = 2048;  // wedge bound for the hash bucket
-  int c4_med_max = 12288;   // wedge bound for the medium hash bucket (0: none)
+  int c4_med_max = 6144;    // wedge bound for the one-pass medium hash (0: no medium bucket)
   int grid_mult = 8;        // persistent blocks per CU for light kernels
   int batch_variant = 0;    // batched kernel: 0 = 1024 threads / 96 KiB, 1 = 512 / 40 KiB
   int batch_light = 128;    // batched kernel: wedge bound of the wavefront hash
   int hub_min = 32;         // out-degree from which a vertex gets a hub table (0: none)
+  int probe_w = 4;          // weight of a hub-table probe against a scanned element (x 1/3)
+  int c4_med_win = 64;      // ranged medium owners: 16 windows >= this per range (0: none)
 };
 
 // Optional per-launch HIP event pairs (M4_TIMING).

@@ -486,6 +486,7 @@ int count_partitioned(m4_ctx* c, const m4_csr* g, const m4_opts* o, uint64_t out
   M4_HIP(hipMemcpyAsync(c->scal_host, c->scal, sizeof(Scal), hipMemcpyDeviceToHost, s));
   M4_HIP(hipStreamSynchronize(s));
   const Scal& h = *c->scal_host;
+  if (h.err) return set_error(c, M4_EINTERNAL, "4-cycle range plan exceeded its bound");
   if (h.status == 3) return set_error(c, M4_EOVERFLOW, "a count is >= 2^64");
   if (h.status != 0) return set_error(c, M4_EINTERNAL, "closure consistency check failed");
   for (int i = 0; i < 6; i++) out[i] = h.out[i];

@@ -277,6 +277,7 @@ void tri_run(const Prep& P, Scal* scal, const Tuning& tu, uint32_t flags, uint32
     A.hoff = hoff;
     A.htab = htab;
     A.hub_min = tu.hub_min;
+    A.probe_w = tu.probe_w;
     if (kt) kt->end(M4_K_TRI_HUBS, s);
   }
 

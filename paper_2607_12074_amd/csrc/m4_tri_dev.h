@@ -44,6 +44,7 @@ struct TriArgs {
   const int32_t* hoff;    // table offset per vertex, -1 without a table
   const unsigned long long* htab;
   int hub_min;            // 0: no tables
+  int probe_w;            // row i is probed when probe_w (k-1-i) < 3 |N+(a[i])|
 };
 
 constexpr unsigned long long HUB_EMPTY = ~0ull;
@@ -89,9 +90,11 @@ __device__ __forceinline__ uint64_t k4_recompute(const int32_t* ncol, const int3
 // (hk/hv, 2H >= 2k slots) instead of a binary search over a[].
 // PROBE: a row i whose head v = a[i] has a hub table is resolved by probing
 // that table for the later entries a[i+1..k) when that is cheaper than
-// scanning N+(v) (k-1-i probes at about 4/3 reads each against |N+(v)|
-// reads); the table returns the position of the hit in N+(v), which indexes
-// the far edge's triangle count.  Both ways find the same triangles.
+// scanning N+(v): k-1-i probes, each weighted probe_w / 3 scanned elements
+// (4/3 reads per probe at load 1/2; larger weights account for a probe
+// fetching a whole cache line where a scan streams 4 bytes); the table
+// returns the position of the hit in N+(v), which indexes the far edge's
+// triangle count.  Both ways find the same triangles.
 // Work counters: steps (elements looked up or probed), looks/hits (frontier
 // cache), ksum (out-list entries of the owner), escan (sum of |N+(v)| over the
 // owner's out-neighbours v, the elements a scanning intersection reads),
@@ -118,7 +121,7 @@ __device__ __forceinline__ void tri_owner(const TriArgs& A, int32_t u, const int
     a[i] = v;
     const int L = A.dplus[v];
     int32_t st = (int32_t)(A.nptr[v] + A.dlo[v]);
-    if (PROBE && A.hub_min > 0 && L >= A.hub_min && 4 * (k - 1 - i) < 3 * L) {
+    if (PROBE && A.hub_min > 0 && L >= A.hub_min && A.probe_w * (k - 1 - i) < 3 * L) {
       const int32_t off = A.hoff[v];
       if (off >= 0) st = -1 - off;  // probe row: table offset, negated
     }

@@ -35,6 +35,8 @@ void to_public(const Tuning& t, m4_tuning* out) {
   out->batch_light = t.batch_light;
   out->hub_min = t.hub_min;
   out->c4_med_max = t.c4_med_max;
+  out->probe_w = t.probe_w;
+  out->c4_med_win = t.c4_med_win;
 }
 
 }  // namespace
@@ -51,7 +53,8 @@ extern "C" int m4_set_tuning(m4_ctx* ctx, const m4_tuning* t) {
       t->c4_light_max > C4_HASH_SLOTS / 2 || (t->batch_variant != 0 && t->batch_variant != 1) ||
       t->batch_light < 1 || t->batch_light > 256 ||
       (t->hub_min != 0 && (t->hub_min < 4 || t->hub_min > 65536)) || t->c4_med_max < 0 ||
-      t->c4_med_max > 3 * C4_MED_SLOTS / 4)
+      t->c4_med_max > 3 * C4_MED_SLOTS / 4 || t->probe_w < 1 || t->probe_w > 256 ||
+      t->c4_med_win < 0 || t->c4_med_win > 65536)
     return set_error(ctx, M4_EINVAL, "tuning value out of range");
   ctx->tune.tri_wave_max = t->tri_wave_max;
   ctx->tune.c4_light_max = t->c4_light_max;
@@ -59,6 +62,8 @@ extern "C" int m4_set_tuning(m4_ctx* ctx, const m4_tuning* t) {
   ctx->tune.batch_light = t->batch_light;
   ctx->tune.hub_min = t->hub_min;
   ctx->tune.c4_med_max = t->c4_med_max;
+  ctx->tune.probe_w = t->probe_w;
+  ctx->tune.c4_med_win = t->c4_med_win;
   return M4_OK;
 }
 
@@ -104,8 +109,9 @@ extern "C" int m4_autotune(m4_ctx* ctx, const m4_csr* graph, const m4_batch* bat
         }
         return rc;
       };
-      // bucket bounds first, then the hub-table threshold, then the medium
-      // 4-cycle bucket, each at the best setting found so far
+      // bucket bounds first, then the hub-table threshold with the probe
+      // weight, then the medium 4-cycle bucket, each at the best setting
+      // found so far
       const int waves[] = {16, 32, 64};
       const int lights[] = {256, 512, 1024, 2048};
       for (int w : waves)
@@ -120,27 +126,35 @@ extern "C" int m4_autotune(m4_ctx* ctx, const m4_csr* graph, const m4_batch* bat
           }
         }
       const int hub_mins[] = {0, 16, 32, 64, 128};
+      const int probe_ws[] = {4, 8, 16, 32};
       const Tuning after_buckets = best;
-      for (int hm : hub_mins) {
-        Tuning t = after_buckets;
-        t.hub_min = hm;
-        const int rc = try_cfg(t);
-        if (rc != M4_OK) {
-          ctx->tune = start;
-          return rc;
+      for (int hm : hub_mins)
+        for (int pw : probe_ws) {
+          if (hm == 0 && pw != probe_ws[0]) continue;  // no tables: the weight is unused
+          Tuning t = after_buckets;
+          t.hub_min = hm;
+          t.probe_w = pw;
+          const int rc = try_cfg(t);
+          if (rc != M4_OK) {
+            ctx->tune = start;
+            return rc;
+          }
         }
-      }
       const int meds[] = {0, 6144, 12288};
+      const int med_wins[] = {0, 32, 64, 128};
       const Tuning after_hubs = best;
-      for (int md : meds) {
-        Tuning t = after_hubs;
-        t.c4_med_max = md;
-        const int rc = try_cfg(t);
-        if (rc != M4_OK) {
-          ctx->tune = start;
-          return rc;
+      for (int md : meds)
+        for (int mw : med_wins) {
+          if (md == 0 && mw != med_wins[0]) continue;  // no medium bucket at all
+          Tuning t = after_hubs;
+          t.c4_med_max = md;
+          t.c4_med_win = mw;
+          const int rc = try_cfg(t);
+          if (rc != M4_OK) {
+            ctx->tune = start;
+            return rc;
+          }
         }
-      }
       ctx->tune = start;
     }
     if (batch) {

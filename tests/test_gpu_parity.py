@@ -153,6 +153,30 @@ def test_threshold_sweep_identical(ctx):
         assert got == ref, (cl, md)
 
 
+def test_medium_bucket_rank_ranges(ctx):
+    # owners with wedge bounds above 3/4 of the medium table are counted over
+    # rank ranges: K_{30,2000} (several endpoints per range), K_{8,9000} (one
+    # endpoint bin above the range capacity), and an R-MAT graph whose owners
+    # span more ranks than the table has bins; c4_med_win=1 sends every
+    # owner with a bound up to 65536 there, whatever its window count
+    import paper_2607_12074_amd as m4
+    med = m4.KERNELS.index("c4_med")
+    saved = ctx.get_tuning()
+    try:
+        for g in (G.complete_bipartite(30, 2000), G.complete_bipartite(8, 9000),
+                  gg.rmat(16, 12, 0.57, 0.19, 0.19, 21)):
+            ref = oracle.closure(*g)
+            seen = []
+            for md, mw in ((-1, 0), (12288, 0), (12288, 1)):
+                ctx.set_tuning(c4_med_win=mw)
+                got, st = ctx.count(*g, c4_med_max=md, stats=True)
+                assert got == ref, (md, mw)
+                seen.append(st["k_rows"][med])
+            assert seen[0] == 0 and seen[2] > seen[1]
+    finally:
+        ctx.set_tuning(**saved)
+
+
 def test_device_tensor_input(ctx):
     import torch
     g = gg.rmat(12, 10, 0.57, 0.19, 0.19, 8)
