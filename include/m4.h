@@ -67,6 +67,9 @@ typedef struct {
 #define M4_FORCE_PARTITION 0x4u /* take the halo-partition path even if it fits      */
 #define M4_STATS 0x8u           /* fill the work counters of m4_stats               */
 #define M4_TIMING 0x10u         /* time every kernel launch with HIP events         */
+#define M4_SERIAL 0x40u         /* single graph: run the triangle and 4-cycle stages
+                                   one after the other on one stream (by default
+                                   they overlap on two streams)                    */
 #define M4_PLAIN_LOOP 0x20u     /* m4_count_batch: one single-graph call per graph
                                    (the reference point of the batched launch)     */
 
@@ -98,6 +101,7 @@ enum {
   M4_K_C4_HASH,       /* ... small wedge bound, 4096-slot LDS hash table       */
   M4_K_CLOSURE,       /* closure sums and exact inverse                         */
   M4_K_TRI_HUBS,      /* hub tables of the long out-lists (triangle probes)     */
+  M4_K_C4_DESC,       /* 4-cycle window owners' segment descriptors             */
   M4_NK = 16
 };
 

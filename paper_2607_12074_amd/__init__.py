@@ -22,9 +22,10 @@ LIB_PATH = os.path.join(HERE, "libm4.so")
 M4_OK, M4_EINVAL, M4_ERANGE, M4_EOVERFLOW, M4_ENOMEM, M4_EDEVICE, M4_EBUSY, M4_EINTERNAL = range(8)
 M4_VALIDATE, M4_NO_CACHE, M4_FORCE_PARTITION, M4_STATS, M4_TIMING = 0x1, 0x2, 0x4, 0x8, 0x10
 M4_PLAIN_LOOP = 0x20
+M4_SERIAL = 0x40
 M4_NK = 16
 KERNELS = ("build", "tri_global", "tri_1024", "tri_512", "tri_256", "tri_128", "tri_wave",
-           "c4_plan", "c4_window", "c4_med", "c4_hash", "closure", "tri_hubs")
+           "c4_plan", "c4_window", "c4_med", "c4_hash", "closure", "tri_hubs", "c4_desc")
 NAMES = ("star", "path", "paw", "cycle", "diamond", "clique")
 BASIS = ("T", "K4", "C4_ni", "S", "P_ni", "Paw_ni", "D_ni", "sum_t")
 

@@ -80,9 +80,13 @@ size_t stage_tmp_bytes(int64_t n, int64_t nnz, int64_t dmax, int num_cu) {
                align256((size_t)(n + 1) * 8 + 8) + align256(scan_tmp_elems(n) * 8) + 4096;
   (void)dmax;
   (void)num_cu;
-  size_t c4 = 2 * align256((size_t)(n + 1) * 8 + 8) + 4 * align256((size_t)n * 4 + 4) +
-              align256(radix_tmp_elems(n, 2) * 8) + align256(scan_tmp_elems(n) * 8) + 4096;
-  return std::max(build, std::max(tri, c4)) + (1 << 16);
+  // the triangle and 4-cycle stages hold their workspaces at the same time
+  return std::max(build, tri + c4_tmp_bytes(n)) + (1 << 16);
+}
+
+size_t c4_tmp_bytes(int64_t n) {
+  return 2 * align256((size_t)(n + 1) * 8 + 8) + 4 * align256((size_t)n * 4 + 4) +
+         align256(radix_tmp_elems(n, 2) * 8) + align256(scan_tmp_elems(n) * 8) + 4096;
 }
 
 int set_error(m4_ctx* ctx, int code, const std::string& msg) {
@@ -110,6 +114,9 @@ extern "C" int m4_ctx_create(int device, m4_ctx** out) {
     c->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     c->arch = std::string(prop.gcnArchName) + " " + std::to_string(c->num_cu) + " CU";
     M4_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    M4_HIP(hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking));
+    M4_HIP(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
+    M4_HIP(hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming));
     M4_HIP(hipMalloc((void**)&c->scal, sizeof(Scal)));
     M4_HIP(hipHostMalloc((void**)&c->scal_host, sizeof(Scal), hipHostMallocDefault));
     for (int i = 0; i < kNumEvents; i++) M4_HIP(hipEventCreate(&c->ev[i]));
@@ -128,9 +135,11 @@ extern "C" void m4_ctx_destroy(m4_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  if (c->stream2) (void)hipStreamSynchronize(c->stream2);
   c->prep.release();
   c->tmp.release();
   c->big.release();
+  c->big2.release();
   c->input.release();
   c->tout.release();
   c->extra.release();
@@ -141,6 +150,9 @@ extern "C" void m4_ctx_destroy(m4_ctx* c) {
   for (int k = 0; k < M4_NK; k++)
     for (int j = 0; j < 2; j++)
       if (c->ktimer.ev[k][j]) (void)hipEventDestroy(c->ktimer.ev[k][j]);
+  if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
+  if (c->join_ev) (void)hipEventDestroy(c->join_ev);
+  if (c->stream2) (void)hipStreamDestroy(c->stream2);
   if (c->stream) (void)hipStreamDestroy(c->stream);
   destroy_ctx_extras(c);
   delete c;
@@ -242,14 +254,36 @@ void run_resident(m4_ctx* c, const int64_t* rp, const int32_t* col, int64_t n, i
     c->big.ensure(bytes, s);
     return c->big.ptr;
   };
-  a.used = 0;
-  tri_run(P, c->scal, tu, flags, cache_rows, a, s, c->num_cu, big, kt);
-  if (want_timing) M4_HIP(hipEventRecord(c->ev[2], s));
-  c->tmp.ensure(stage_tmp_bytes(n, nnz, C.dmax, c->num_cu), s);
-  a.base = c->tmp.ptr;
-  a.cap = c->tmp.cap;
-  a.used = 0;
-  c4_run(P, C, c->scal, tu, flags, a, s, c->num_cu, kt, big);
+  auto big2 = [c, s](size_t bytes) -> char* {
+    c->big2.ensure(bytes, s);
+    return c->big2.ptr;
+  };
+  // both anchor stages are planned first, each in its own part of the
+  // workspace; their heavy kernels then run concurrently, the 4-cycle stage
+  // on the context's second stream (forked from and joined back into s), so
+  // that each fills the CUs the other's tail leaves idle (triangle kernels
+  // are queued first: measured slightly ahead of the reverse order)
+  const size_t c4_bytes = c4_tmp_bytes(n);
+  Arena at, ac;
+  at.base = c->tmp.ptr;
+  at.cap = c->tmp.cap - c4_bytes;
+  ac.base = c->tmp.ptr + at.cap;
+  ac.cap = c4_bytes;
+  Launch tri = tri_plan(P, c->scal, tu, flags, cache_rows, at, s, c->num_cu, big, kt);
+  Launch c4 = c4_plan(P, C, c->scal, tu, flags, ac, s, c->num_cu, kt, big2);
+  if (flags & M4_SERIAL) {
+    tri(s);
+    if (want_timing) M4_HIP(hipEventRecord(c->ev[2], s));
+    c4(s);
+  } else {
+    M4_HIP(hipEventRecord(c->fork_ev, s));
+    M4_HIP(hipStreamWaitEvent(c->stream2, c->fork_ev, 0));
+    tri(s);
+    c4(c->stream2);
+    if (want_timing) M4_HIP(hipEventRecord(c->ev[2], s));
+    M4_HIP(hipEventRecord(c->join_ev, c->stream2));
+    M4_HIP(hipStreamWaitEvent(s, c->join_ev, 0));
+  }
   if (want_timing) M4_HIP(hipEventRecord(c->ev[3], s));
   if (kt) kt->begin(M4_K_CLOSURE, s);
   closure_run(P, c->scal, flags, s);

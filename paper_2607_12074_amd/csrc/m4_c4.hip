@@ -29,6 +29,7 @@
 #include <limits.h>
 
 #include <algorithm>
+#include <array>
 #include <type_traits>
 
 #include "m4_device.h"
@@ -740,11 +741,11 @@ inline unsigned blocks_for(int64_t n, int nt) { return (unsigned)ceil_div(n > 0 
 
 }  // namespace
 
-void c4_run(const Prep& P, const Classes& C, Scal* scal, const Tuning& tu, uint32_t flags,
-            Arena& tmp, hipStream_t s, int num_cu, KTimer* kt,
-            const std::function<char*(size_t)>& big_scratch) {
+Launch c4_plan(const Prep& P, const Classes& C, Scal* scal, const Tuning& tu, uint32_t flags,
+               Arena& tmp, hipStream_t s, int num_cu, KTimer* kt,
+               const std::function<char*(size_t)>& big_scratch) {
   const int64_t n = P.n;
-  if (n == 0 || P.m == 0) return;
+  if (n == 0 || P.m == 0) return [](hipStream_t) {};
   int64_t* wub = tmp.take<int64_t>(n);
   uint32_t* key = tmp.take<uint32_t>(n);
   int32_t* order = tmp.take<int32_t>(n);
@@ -756,7 +757,7 @@ void c4_run(const Prep& P, const Classes& C, Scal* scal, const Tuning& tu, uint3
   int32_t* lowcut = tmp.take<int32_t>(n);
   if (!wub || !key || !order || !rtmp || !start || !hlen || !seg_off || !stmp || !lowcut)
     throw Fail(M4_EINTERNAL, "workspace too small (c4)");
-  fill_u32(&scal->work[0], 0, 8, s);
+  fill_u32(&scal->work_c4[0], 0, 8, s);
   // zone bounds first: the planner needs every owner's window count
   k_zone_bounds<<<1, 64, 0, s>>>(P.dr, n, start + CB_N + 1);
   C4Plan pl{tu.c4_light_max, tu.c4_med_max, tu.c4_med_win, start + CB_N + 1, C.r1};
@@ -774,8 +775,9 @@ void c4_run(const Prep& P, const Classes& C, Scal* scal, const Tuning& tu, uint3
     k_c4_plan_big<<<(unsigned)(n - b4096), 1024, 0, s>>>(P.nptr, P.ncol, P.dr, P.dlo, b4096, C.r1,
                                                          pl, wub, key, P.own_lo, P.hi());
   radix_pass(key, nullptr, n, 0, 2, nullptr, order, rtmp, start, s);
-  int64_t hstart[CB_N + 3];
-  M4_HIP(hipMemcpyAsync(hstart, start, sizeof(hstart), hipMemcpyDeviceToHost, s));
+  std::array<int64_t, CB_N + 3> hstart;
+  M4_HIP(hipMemcpyAsync(hstart.data(), start, sizeof(int64_t) * hstart.size(),
+                        hipMemcpyDeviceToHost, s));
   M4_HIP(hipStreamSynchronize(s));
   // counter zones of the window owners
   const int64_t z1 = std::max<int64_t>(hstart[CB_N + 1], C.r1);
@@ -791,11 +793,6 @@ void c4_run(const Prep& P, const Classes& C, Scal* scal, const Tuning& tu, uint3
     M4_HIP(hipStreamSynchronize(s));
     desc = reinterpret_cast<int4*>(big_scratch((size_t)(nseg > 0 ? nseg : 1) * sizeof(int4)));
     if (!desc) throw Fail(M4_ENOMEM, "no room for 4-cycle segment descriptors");
-    // with stored prefixes only the partition's rows are valid: no full pass
-    if (!P.row_len)
-      k_lowcut<<<blocks_for(n, 256), 256, 0, s>>>(P.nptr, P.ncol, P.row_len, n, C.r1, lowcut);
-    k_c4_desc<<<(unsigned)H, 256, 0, s>>>(order, start, seg_off, P.nptr, P.dlo, P.ncol,
-                                          P.row_len ? nullptr : lowcut, P.row_len, C.r1, desc);
   }
   if (kt) kt->end(M4_K_C4_PLAN, s);
 
@@ -818,31 +815,44 @@ void c4_run(const Prep& P, const Classes& C, Scal* scal, const Tuning& tu, uint3
   A.aw = (int32_t)aw;
   A.bw = (int32_t)bw;
   A.zr1 = (int32_t)C.r1;
-  // heavy owners first: one 1024-thread workgroup per CU
-  if (hstart[CB_WIN + 1] > hstart[CB_WIN]) {
-    A.bucket = CB_WIN;
-    A.slot = M4_K_C4_WINDOW;
-    A.work = &scal->work[CB_WIN];
-    if (kt) kt->begin(M4_K_C4_WINDOW, s);
-    k_c4_window<<<(unsigned)num_cu, W_NT, 0, s>>>(A);
-    if (kt) kt->end(M4_K_C4_WINDOW, s);
-  }
-  if (hstart[CB_MED + 1] > hstart[CB_MED]) {
-    A.bucket = CB_MED;
-    A.slot = M4_K_C4_MED;
-    A.work = &scal->work[CB_MED];
-    if (kt) kt->begin(M4_K_C4_MED, s);
-    k_c4_hash<1024, C4_MED_SLOTS, 4><<<(unsigned)num_cu, 1024, 0, s>>>(A);
-    if (kt) kt->end(M4_K_C4_MED, s);
-  }
-  if (hstart[CB_HASH + 1] > hstart[CB_HASH]) {
-    A.bucket = CB_HASH;
-    A.slot = M4_K_C4_HASH;
-    A.work = &scal->work[CB_HASH];
-    if (kt) kt->begin(M4_K_C4_HASH, s);
-    k_c4_hash<256, C4_HASH_SLOTS, 4><<<(unsigned)(num_cu * 4), 256, 0, s>>>(A);
-    if (kt) kt->end(M4_K_C4_HASH, s);
-  }
+  // everything below runs on the launch stream, after the plan above
+  return [=](hipStream_t ls) mutable {
+    if (H > 0) {
+      if (kt) kt->begin(M4_K_C4_DESC, ls);
+      // with stored prefixes only the partition's rows are valid: no full pass
+      if (!P.row_len)
+        k_lowcut<<<blocks_for(n, 256), 256, 0, ls>>>(P.nptr, P.ncol, P.row_len, n, C.r1, lowcut);
+      k_c4_desc<<<(unsigned)H, 256, 0, ls>>>(order, start, seg_off, P.nptr, P.dlo, P.ncol,
+                                             P.row_len ? nullptr : lowcut, P.row_len, C.r1,
+                                             desc);
+      if (kt) kt->end(M4_K_C4_DESC, ls);
+    }
+    // heavy owners first: one 1024-thread workgroup per CU
+    if (hstart[CB_WIN + 1] > hstart[CB_WIN]) {
+      A.bucket = CB_WIN;
+      A.slot = M4_K_C4_WINDOW;
+      A.work = &scal->work_c4[CB_WIN];
+      if (kt) kt->begin(M4_K_C4_WINDOW, ls);
+      k_c4_window<<<(unsigned)num_cu, W_NT, 0, ls>>>(A);
+      if (kt) kt->end(M4_K_C4_WINDOW, ls);
+    }
+    if (hstart[CB_MED + 1] > hstart[CB_MED]) {
+      A.bucket = CB_MED;
+      A.slot = M4_K_C4_MED;
+      A.work = &scal->work_c4[CB_MED];
+      if (kt) kt->begin(M4_K_C4_MED, ls);
+      k_c4_hash<1024, C4_MED_SLOTS, 4><<<(unsigned)num_cu, 1024, 0, ls>>>(A);
+      if (kt) kt->end(M4_K_C4_MED, ls);
+    }
+    if (hstart[CB_HASH + 1] > hstart[CB_HASH]) {
+      A.bucket = CB_HASH;
+      A.slot = M4_K_C4_HASH;
+      A.work = &scal->work_c4[CB_HASH];
+      if (kt) kt->begin(M4_K_C4_HASH, ls);
+      k_c4_hash<256, C4_HASH_SLOTS, 4><<<(unsigned)(num_cu * 4), 256, 0, ls>>>(A);
+      if (kt) kt->end(M4_K_C4_HASH, ls);
+    }
+  };
 }
 
 }  // namespace m4

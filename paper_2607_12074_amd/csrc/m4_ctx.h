@@ -22,6 +22,7 @@ struct PartState;
 size_t prep_bytes(int64_t n, int64_t nnz);
 Prep carve_prep(char* base, int64_t n, int64_t nnz);
 size_t stage_tmp_bytes(int64_t n, int64_t nnz, int64_t dmax, int num_cu);
+size_t c4_tmp_bytes(int64_t n);
 int set_error(m4_ctx* ctx, int code, const std::string& msg);
 int check_csr_args(const m4_csr* g);
 Tuning tuning_for(const m4_ctx* c, const m4_opts* o);
@@ -55,7 +56,9 @@ struct m4_ctx {
   hipStream_t stream = nullptr;
   m4::Scal* scal = nullptr;       // device
   m4::Scal* scal_host = nullptr;  // pinned
-  m4::DevBuf prep, tmp, big, input, tout, extra;
+  hipStream_t stream2 = nullptr;  // the 4-cycle stage, overlapped with the triangle stage
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  m4::DevBuf prep, tmp, big, big2, input, tout, extra;
   hipEvent_t ev[m4::kNumEvents] = {};
   m4::KTimer ktimer;
   m4::Tuning tune;

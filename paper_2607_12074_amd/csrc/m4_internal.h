@@ -46,7 +46,8 @@ struct Scal {
   unsigned long long stat[ST_N];
   unsigned int dmax;
   int err;
-  unsigned int work[8];
+  unsigned int work[8];     // owner counters of the triangle stage
+  unsigned int work_c4[8];  // ... of the 4-cycle stage (the stages may overlap)
   unsigned int nhub;  // vertices with a hub table (triangle stage)
   unsigned int pad2;
   int64_t tri_start[TB_N + 1];
@@ -193,18 +194,34 @@ void sort_rows(const int64_t* rp, const int32_t* col, const int32_t* perm, const
 int row_class_count();
 const int* row_class_thresholds();
 
+// An anchor stage is planned on stream s (small kernels and host read-backs
+// of bucket sizes) and returns the launches of its heavy kernels, to be
+// issued on any stream ordered after s; the stage's workspace and scratch
+// stay reserved until those kernels are done.
+using Launch = std::function<void(hipStream_t)>;
+
 // m4_tri.hip
 size_t tri_tmp_bytes(int64_t n, int64_t nnz, int dplus_max_bound);
-// big_scratch(bytes) returns device memory for owners whose bitmap does not
-// fit in LDS (only called when such owners exist).
-void tri_run(const Prep& P, Scal* scal, const Tuning& tu, uint32_t flags, uint32_t cache_rows,
-             Arena& tmp, hipStream_t s, int num_cu,
-             const std::function<char*(size_t)>& big_scratch, KTimer* kt);
+// big_scratch(bytes) returns device memory for the hub tables and for owners
+// whose bitmap does not fit in LDS (only called when those exist).
+Launch tri_plan(const Prep& P, Scal* scal, const Tuning& tu, uint32_t flags, uint32_t cache_rows,
+                Arena& tmp, hipStream_t s, int num_cu,
+                const std::function<char*(size_t)>& big_scratch, KTimer* kt);
+inline void tri_run(const Prep& P, Scal* scal, const Tuning& tu, uint32_t flags,
+                    uint32_t cache_rows, Arena& tmp, hipStream_t s, int num_cu,
+                    const std::function<char*(size_t)>& big_scratch, KTimer* kt) {
+  tri_plan(P, scal, tu, flags, cache_rows, tmp, s, num_cu, big_scratch, kt)(s);
+}
 
 // m4_c4.hip
-void c4_run(const Prep& P, const Classes& C, Scal* scal, const Tuning& tu, uint32_t flags,
-            Arena& tmp, hipStream_t s, int num_cu, KTimer* kt,
-            const std::function<char*(size_t)>& big_scratch);
+Launch c4_plan(const Prep& P, const Classes& C, Scal* scal, const Tuning& tu, uint32_t flags,
+               Arena& tmp, hipStream_t s, int num_cu, KTimer* kt,
+               const std::function<char*(size_t)>& big_scratch);
+inline void c4_run(const Prep& P, const Classes& C, Scal* scal, const Tuning& tu, uint32_t flags,
+                   Arena& tmp, hipStream_t s, int num_cu, KTimer* kt,
+                   const std::function<char*(size_t)>& big_scratch) {
+  c4_plan(P, C, scal, tu, flags, tmp, s, num_cu, kt, big_scratch)(s);
+}
 
 // m4_closure.hip
 void closure_run(const Prep& P, Scal* scal, uint32_t flags, hipStream_t s);

@@ -18,6 +18,8 @@
 // per workgroup (block-local aggregation).
 #include <limits.h>
 
+#include <array>
+
 #include "m4_tri_dev.h"
 
 namespace m4 {
@@ -191,11 +193,11 @@ size_t tri_tmp_bytes(int64_t n, int64_t nnz, int kmax_global) {
              ((size_t)kmax_global * ((kmax_global + 63) / 64) * 8 + (7 * (size_t)kmax_global + 2) * 4);
 }
 
-void tri_run(const Prep& P, Scal* scal, const Tuning& tu, uint32_t flags, uint32_t cache_rows,
-             Arena& tmp, hipStream_t s, int num_cu,
-             const std::function<char*(size_t)>& big_scratch, KTimer* kt) {
+Launch tri_plan(const Prep& P, Scal* scal, const Tuning& tu, uint32_t flags, uint32_t cache_rows,
+                Arena& tmp, hipStream_t s, int num_cu,
+                const std::function<char*(size_t)>& big_scratch, KTimer* kt) {
   const int64_t n = P.n;
-  if (n == 0 || P.m == 0) return;
+  if (n == 0 || P.m == 0) return [](hipStream_t) {};
   uint32_t* key = tmp.take<uint32_t>(n);
   int32_t* order = tmp.take<int32_t>(n);
   int64_t* rtmp = tmp.take<int64_t>(radix_tmp_elems(n, 4));
@@ -267,57 +269,59 @@ void tri_run(const Prep& P, Scal* scal, const Tuning& tu, uint32_t flags, uint32
   A.scal = scal;
   A.flags = flags;
   A.cache_rows = cache_rows;
-  if (use_hubs) {
-    if (kt) kt->begin(M4_K_TRI_HUBS, s);
-    unsigned long long* htab = reinterpret_cast<unsigned long long*>(scratch);
-    k_hub_off<<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(hsz, hoff64, n, hoff);
-    fill_u32(htab, 0xffffffffu, (size_t)hub_slots * 2, s);
-    k_hub_insert<<<(unsigned)(num_cu * 8), 256, 0, s>>>(P.dplus, P.nptr, P.dlo, P.ncol, hoff,
-                                                         hub_list, &scal->nhub, htab);
-    A.hoff = hoff;
-    A.htab = htab;
-    A.hub_min = tu.hub_min;
-    A.probe_w = tu.probe_w;
-    if (kt) kt->end(M4_K_TRI_HUBS, s);
-  }
-
-  auto run_lds = [&](auto kmax_tag, auto nt_tag, int bucket, int slot, int blocks_per_cu) {
-    constexpr int KM = decltype(kmax_tag)::value;
-    constexpr int NT = decltype(nt_tag)::value;
-    if (hstart[bucket + 1] == hstart[bucket]) return;
-    A.bucket = bucket;
-    A.slot = slot;
-    A.work = &scal->work[bucket];
-    A.grab = KM <= 64 ? 16 : (KM <= 128 ? 4 : 1);
-    int64_t blocks = (int64_t)num_cu * blocks_per_cu;
-    if (blocks > hstart[bucket + 1] - hstart[bucket]) blocks = hstart[bucket + 1] - hstart[bucket];
-    if (kt) kt->begin(slot, s);
-    k_tri_lds<KM, NT><<<(unsigned)blocks, NT, 0, s>>>(A);
-    if (kt) kt->end(slot, s);
+  std::array<int64_t, 17> hst;
+  for (int i = 0; i < 17; i++) hst[i] = hstart[i];
+  // everything below runs on the launch stream, after the plan above
+  return [=](hipStream_t ls) mutable {
+    if (use_hubs) {
+      if (kt) kt->begin(M4_K_TRI_HUBS, ls);
+      unsigned long long* htab = reinterpret_cast<unsigned long long*>(scratch);
+      k_hub_off<<<(unsigned)ceil_div(n, 256), 256, 0, ls>>>(hsz, hoff64, n, hoff);
+      fill_u32(htab, 0xffffffffu, (size_t)hub_slots * 2, ls);
+      k_hub_insert<<<(unsigned)(num_cu * 8), 256, 0, ls>>>(P.dplus, P.nptr, P.dlo, P.ncol, hoff,
+                                                            hub_list, &scal->nhub, htab);
+      A.hoff = hoff;
+      A.htab = htab;
+      A.hub_min = tu.hub_min;
+      A.probe_w = tu.probe_w;
+      if (kt) kt->end(M4_K_TRI_HUBS, ls);
+    }
+    auto run_lds = [&](auto kmax_tag, auto nt_tag, int bucket, int slot, int blocks_per_cu) {
+      constexpr int KM = decltype(kmax_tag)::value;
+      constexpr int NT = decltype(nt_tag)::value;
+      if (hst[bucket + 1] == hst[bucket]) return;
+      A.bucket = bucket;
+      A.slot = slot;
+      A.work = &scal->work[bucket];
+      A.grab = KM <= 64 ? 16 : (KM <= 128 ? 4 : 1);
+      int64_t blocks = (int64_t)num_cu * blocks_per_cu;
+      if (blocks > hst[bucket + 1] - hst[bucket]) blocks = hst[bucket + 1] - hst[bucket];
+      if (kt) kt->begin(slot, ls);
+      k_tri_lds<KM, NT><<<(unsigned)blocks, NT, 0, ls>>>(A);
+      if (kt) kt->end(slot, ls);
+    };
+    // heaviest buckets first so that their tails overlap the light ones
+    if (kmax_g > 0) {
+      const size_t K = kmax_g;
+      A.bucket = TK_GLOBAL;
+      A.slot = M4_K_TRI_GLOBAL;
+      A.grab = 1;
+      A.work = &scal->work[TK_GLOBAL];
+      A.kmax = (int)K;
+      A.gbits = reinterpret_cast<uint64_t*>(scratch + hub_bytes);
+      A.garr = reinterpret_cast<int32_t*>(scratch + hub_bytes + dense_bits);
+      if (kt) kt->begin(M4_K_TRI_GLOBAL, ls);
+      k_tri_global<256><<<(unsigned)dense_blocks, 256, 0, ls>>>(A);
+      if (kt) kt->end(M4_K_TRI_GLOBAL, ls);
+    }
+    using std::integral_constant;
+    run_lds(integral_constant<int, 1024>{}, integral_constant<int, 256>{}, TK_1024, M4_K_TRI_1024,
+            1);
+    run_lds(integral_constant<int, 512>{}, integral_constant<int, 256>{}, TK_512, M4_K_TRI_512, 3);
+    run_lds(integral_constant<int, 256>{}, integral_constant<int, 256>{}, TK_256, M4_K_TRI_256, 8);
+    run_lds(integral_constant<int, 128>{}, integral_constant<int, 256>{}, TK_128, M4_K_TRI_128, 8);
+    run_lds(integral_constant<int, 64>{}, integral_constant<int, 64>{}, TK_WAVE, M4_K_TRI_WAVE, 32);
   };
-  // heaviest buckets first so that their tails overlap the light ones
-  if (kmax_g > 0) {
-    size_t K = kmax_g;
-    uint64_t* gbits = reinterpret_cast<uint64_t*>(scratch + hub_bytes);
-    int32_t* garr = reinterpret_cast<int32_t*>(scratch + hub_bytes + dense_bits);
-    const int64_t blocks = (int64_t)dense_blocks;
-    A.bucket = TK_GLOBAL;
-    A.slot = M4_K_TRI_GLOBAL;
-    A.grab = 1;
-    A.work = &scal->work[TK_GLOBAL];
-    A.kmax = (int)K;
-    A.gbits = gbits;
-    A.garr = garr;
-    if (kt) kt->begin(M4_K_TRI_GLOBAL, s);
-    k_tri_global<256><<<(unsigned)blocks, 256, 0, s>>>(A);
-    if (kt) kt->end(M4_K_TRI_GLOBAL, s);
-  }
-  using std::integral_constant;
-  run_lds(integral_constant<int, 1024>{}, integral_constant<int, 256>{}, TK_1024, M4_K_TRI_1024, 1);
-  run_lds(integral_constant<int, 512>{}, integral_constant<int, 256>{}, TK_512, M4_K_TRI_512, 3);
-  run_lds(integral_constant<int, 256>{}, integral_constant<int, 256>{}, TK_256, M4_K_TRI_256, 8);
-  run_lds(integral_constant<int, 128>{}, integral_constant<int, 256>{}, TK_128, M4_K_TRI_128, 8);
-  run_lds(integral_constant<int, 64>{}, integral_constant<int, 64>{}, TK_WAVE, M4_K_TRI_WAVE, 32);
 }
 
 }  // namespace m4

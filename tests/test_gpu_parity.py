@@ -177,6 +177,22 @@ def test_medium_bucket_rank_ranges(ctx):
         ctx.set_tuning(**saved)
 
 
+def test_serial_and_overlapped_stages_agree(ctx):
+    # the triangle and 4-cycle stages overlap on two streams by default;
+    # M4_SERIAL runs them on one: counts, basis and work counters agree
+    import paper_2607_12074_amd as m4
+    g = gg.rmat(16, 12, 0.57, 0.19, 0.19, 23)
+    ref = oracle.closure(*g)
+    b, sb = ctx.count(*g, flags=m4.M4_SERIAL, stats=True)
+    assert b == ref
+    for _ in range(3):
+        a, sa = ctx.count(*g, stats=True)
+        assert a == ref
+        for k in ("T", "K4", "C4_ni", "S", "P_ni", "Paw_ni", "D_ni", "sum_t", "wedges",
+                  "intersect_steps", "cache_lookups"):
+            assert sa[k] == sb[k], k
+
+
 def test_device_tensor_input(ctx):
     import torch
     g = gg.rmat(12, 10, 0.57, 0.19, 0.19, 8)
