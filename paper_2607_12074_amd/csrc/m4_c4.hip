@@ -486,6 +486,29 @@ __device__ __forceinline__ uint32_t window_inc(const C4Args& A, uint32_t* cnt, i
   return (old >> shift) & mask;
 }
 
+// The same increment for a window that lies inside one zone (KIND 0: 4-bit
+// counters, 1: 8-bit, 2: 32-bit; 3: the window crosses a zone bound): with
+// base the first rank of the window's first word, the counter word is
+// (x - base) >> log2(counters per word), so the zone tests and the shifted
+// zone offsets drop out of the per-endpoint work.
+template <int KIND>
+__device__ __forceinline__ uint32_t window_inc_k(const C4Args& A, uint32_t* cnt, int32_t wlo,
+                                                 int32_t base, int32_t x) {
+  if constexpr (KIND == 0) {
+    const int32_t k = x - base;
+    const int sh = (k & 7) << 2;
+    return (atomicAdd(&cnt[k >> 3], 1u << sh) >> sh) & 0xfu;
+  } else if constexpr (KIND == 1) {
+    const int32_t k = x - base;
+    const int sh = (k & 3) << 3;
+    return (atomicAdd(&cnt[k >> 2], 1u << sh) >> sh) & 0xffu;
+  } else if constexpr (KIND == 2) {
+    return atomicAdd(&cnt[x - base], 1u);
+  } else {
+    return window_inc(A, cnt, wlo, x);
+  }
+}
+
 // word holding the counter of rank x (x >= r1)
 __device__ __forceinline__ int32_t zone_word(const C4Args& A, int32_t x) {
   int32_t word;
@@ -505,14 +528,15 @@ __device__ __forceinline__ int32_t comp(const int4& v, int r) {
 // A visit of at most 7 entries by one thread: entries c .. c+14 from five
 // aligned 16-byte loads, the entries below hi counted, the descriptor
 // advanced (the new cursor's value and the one 7 later are among them).
+template <int KIND>
 __device__ __forceinline__ int short_visit(const C4Args& A, const int4* __restrict__ ncol4,
-                                           uint32_t* cnt, int4& d, int32_t wlo, int32_t hi,
-                                           u128_t& acc) {
-  const int64_t c = d.x, e = d.y, base = c & ~int64_t(3);
-  const int off = (int)(c - base);
+                                           uint32_t* cnt, int4& d, int32_t wlo, int32_t base,
+                                           int32_t hi, u128_t& acc) {
+  const int64_t c = d.x, e = d.y, c4 = c & ~int64_t(3);
+  const int off = (int)(c - c4);
   int4 v[5];
 #pragma unroll
-  for (int q = 0; q < 5; q++) v[q] = ncol4[(base >> 2) + q];
+  for (int q = 0; q < 5; q++) v[q] = ncol4[(c4 >> 2) + q];
   int32_t x[W_SHORT + 7];
 #pragma unroll
   for (int j = 0; j < W_SHORT + 7; j++) {
@@ -530,7 +554,7 @@ __device__ __forceinline__ int short_visit(const C4Args& A, const int4* __restri
 #pragma unroll
   for (int j = 0; j < W_SHORT; j++)
     if (x[j] < hi) {
-      part += window_inc(A, cnt, wlo, x[j]);
+      part += window_inc_k<KIND>(A, cnt, wlo, base, x[j]);
       took++;
     }
   acc += part;
@@ -607,116 +631,129 @@ __global__ __launch_bounds__(W_NT) void k_c4_window(C4Args A) {
         visits += (unsigned long long)nl;
         s_minz = INT_MAX;
       }
-      for (int s0 = 0; s0 < nl; s0 += W_BATCH) {
-        const int s1 = s0 + W_BATCH < nl ? s0 + W_BATCH : nl;
-        if (tid == 0) s_q = 0;
-        __syncthreads();
-        // ---- whole segments per thread
-        int32_t zmin = INT_MAX;
-        if (resident) {
-          // descriptors stay in registers across windows; one that a group
-          // advances (a long visit) is stored before and reloaded after
+      // the window's zone: one zone lets the counter index skip the zone tests
+      const int32_t wr = zone_rank(A, wlo);
+      const int kind = hi <= A.z1 ? 0 : (wr >= A.z1 && hi <= A.z2 ? 1 : (wr >= A.z2 ? 2 : 3));
+      const int32_t base = wr;
+      auto pass = [&](auto kind_tag) {
+        constexpr int KIND = decltype(kind_tag)::value;
+        for (int s0 = 0; s0 < nl; s0 += W_BATCH) {
+          const int s1 = s0 + W_BATCH < nl ? s0 + W_BATCH : nl;
+          if (tid == 0) s_q = 0;
+          __syncthreads();
+          // ---- whole segments per thread
+          int32_t zmin = INT_MAX;
+          if (resident) {
+            // descriptors stay in registers across windows; one that a group
+            // advances (a long visit) is stored before and reloaded after
 #pragma unroll
-          for (int j = 0; j < W_RPT; j++) {
-            const int sg = tid + j * W_NT;
-            if (sg < nl) {
-              if ((stale >> j) & 1u) {
-                rdesc[j] = D[sg];
-                stale &= ~(1u << j);
-              }
-              if (rdesc[j].z < hi && rdesc[j].w < hi) {
-                D[sg] = rdesc[j];
-                queue[atomicAdd(&s_q, 1)] = sg;
-                stale |= 1u << j;
-              } else {
-                if (rdesc[j].z < hi)
-                  wedges += short_visit(A, ncol4, cnt, rdesc[j], wlo, hi, acc);
-                zmin = min(zmin, rdesc[j].z);
-              }
-            }
-          }
-        } else {
-          for (int sg = s0 + tid; sg < s1; sg += W_NT) {
-            int4 d = D[sg];
-            if (d.z < hi && d.w < hi) {  // 8 entries or more: queue it
-              queue[atomicAdd(&s_q, 1)] = sg;
-              continue;
-            }
-            if (d.z < hi) {
-              wedges += short_visit(A, ncol4, cnt, d, wlo, hi, acc);
-              D[sg] = d;
-            }
-            zmin = min(zmin, d.z);
-          }
-        }
-        if (zmin != INT_MAX) atomicMin(&s_minz, zmin);
-        __syncthreads();
-        // ---- queued long segments, one 8-lane group each: a step reads the
-        // STEP entries [p, p + STEP); lane gl holds entries
-        // 4 (W_GL k + gl) + r (k < W_LD, r < 4) of the step
-        const int nq = s_q;
-        int qi = g;
-        int4 dA = qi < nq ? D[queue[qi]] : kNone;
-        int64_t pA = (int64_t)dA.x & ~int64_t(STEP - 1);
-        int4 a[W_LD];
-#pragma unroll
-        for (int k = 0; k < W_LD; k++)
-          a[k] = qi < nq ? ncol4[(pA >> 2) + W_GL * k + gl] : make_int4(0, 0, 0, 0);
-        while (qi < nq) {  // uniform in the group
-          const int sg = queue[qi];
-          const int qn = qi + W_NG;
-          const int4 dB = qn < nq ? D[queue[qn]] : kNone;
-          const int64_t pB = (int64_t)dB.x & ~int64_t(STEP - 1);
-          int4 bn[W_LD];
-#pragma unroll
-          for (int k = 0; k < W_LD; k++)
-            bn[k] = qn < nq ? ncol4[(pB >> 2) + W_GL * k + gl] : make_int4(0, 0, 0, 0);
-          const int64_t c0 = dA.x, e = dA.y;
-          int64_t p = pA;
-          int64_t cend = c0;  // new cursor
-          for (;;) {
-            int mine = 0;
-            uint64_t part = 0;  // < 4 W_LD counts of < 2^32 each
-            // the step's entries from the cursor on and before the row end
-            const int lo_o = (int)(c0 > p ? c0 - p : 0);
-            const int hi_o = (int)(e - p < STEP ? e - p : STEP);
-#pragma unroll
-            for (int k = 0; k < W_LD; k++)
-#pragma unroll
-              for (int r = 0; r < 4; r++) {
-                const int32_t xv = comp(a[k], r);
-                const int o = 4 * (W_GL * k + gl) + r;
-                if (o >= lo_o && o < hi_o && xv < hi) {
-                  part += window_inc(A, cnt, wlo, xv);
-                  mine++;
+            for (int j = 0; j < W_RPT; j++) {
+              const int sg = tid + j * W_NT;
+              if (sg < nl) {
+                if ((stale >> j) & 1u) {
+                  rdesc[j] = D[sg];
+                  stale &= ~(1u << j);
+                }
+                if (rdesc[j].z < hi && rdesc[j].w < hi) {
+                  D[sg] = rdesc[j];
+                  queue[atomicAdd(&s_q, 1)] = sg;
+                  stale |= 1u << j;
+                } else {
+                  if (rdesc[j].z < hi)
+                    wedges += short_visit<KIND>(A, ncol4, cnt, rdesc[j], wlo, base, hi, acc);
+                  zmin = min(zmin, rdesc[j].z);
                 }
               }
-            acc += part;
-            wedges += (unsigned long long)mine;
-            // entries in the window form a run from the cursor: its length is
-            // the group's total
-            int tot = mine;
-#pragma unroll
-            for (int o = 1; o < W_GL; o <<= 1) tot += __shfl_xor(tot, o, WAVE);
-            const int64_t first = p > c0 ? p : c0;
-            cend = first + tot;
-            if (cend < p + STEP || p + STEP >= e) break;  // the run ends in this step
-            p += STEP;
-#pragma unroll
-            for (int k = 0; k < W_LD; k++) a[k] = ncol4[(p >> 2) + W_GL * k + gl];
+            }
+          } else {
+            for (int sg = s0 + tid; sg < s1; sg += W_NT) {
+              int4 d = D[sg];
+              if (d.z < hi && d.w < hi) {  // 8 entries or more: queue it
+                queue[atomicAdd(&s_q, 1)] = sg;
+                continue;
+              }
+              if (d.z < hi) {
+                wedges += short_visit<KIND>(A, ncol4, cnt, d, wlo, base, hi, acc);
+                D[sg] = d;
+              }
+              zmin = min(zmin, d.z);
+            }
           }
-          if (gl == 0) {
-            const int32_t vnext = row_at(A.ncol, cend, e);
-            D[sg] = make_int4((int)cend, (int)e, vnext, row_at(A.ncol, cend + 7, e));
-            atomicMin(&s_minz, vnext);
-          }
-          qi = qn;
-          dA = dB;
-          pA = pB;
+          if (zmin != INT_MAX) atomicMin(&s_minz, zmin);
+          __syncthreads();
+          // ---- queued long segments, one 8-lane group each: a step reads the
+          // STEP entries [p, p + STEP); lane gl holds entries
+          // 4 (W_GL k + gl) + r (k < W_LD, r < 4) of the step
+          const int nq = s_q;
+          int qi = g;
+          int4 dA = qi < nq ? D[queue[qi]] : kNone;
+          int64_t pA = (int64_t)dA.x & ~int64_t(STEP - 1);
+          int4 a[W_LD];
 #pragma unroll
-          for (int k = 0; k < W_LD; k++) a[k] = bn[k];
+          for (int k = 0; k < W_LD; k++)
+            a[k] = qi < nq ? ncol4[(pA >> 2) + W_GL * k + gl] : make_int4(0, 0, 0, 0);
+          while (qi < nq) {  // uniform in the group
+            const int sg = queue[qi];
+            const int qn = qi + W_NG;
+            const int4 dB = qn < nq ? D[queue[qn]] : kNone;
+            const int64_t pB = (int64_t)dB.x & ~int64_t(STEP - 1);
+            int4 bn[W_LD];
+#pragma unroll
+            for (int k = 0; k < W_LD; k++)
+              bn[k] = qn < nq ? ncol4[(pB >> 2) + W_GL * k + gl] : make_int4(0, 0, 0, 0);
+            const int64_t c0 = dA.x, e = dA.y;
+            int64_t p = pA;
+            int64_t cend = c0;  // new cursor
+            for (;;) {
+              int mine = 0;
+              uint64_t part = 0;  // < 4 W_LD counts of < 2^32 each
+              // the step's entries from the cursor on and before the row end
+              const int lo_o = (int)(c0 > p ? c0 - p : 0);
+              const int hi_o = (int)(e - p < STEP ? e - p : STEP);
+#pragma unroll
+              for (int k = 0; k < W_LD; k++)
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                  const int32_t xv = comp(a[k], r);
+                  const int o = 4 * (W_GL * k + gl) + r;
+                  if (o >= lo_o && o < hi_o && xv < hi) {
+                    part += window_inc_k<KIND>(A, cnt, wlo, base, xv);
+                    mine++;
+                  }
+                }
+              acc += part;
+              wedges += (unsigned long long)mine;
+              // entries in the window form a run from the cursor: its length is
+              // the group's total
+              int tot = mine;
+#pragma unroll
+              for (int o = 1; o < W_GL; o <<= 1) tot += __shfl_xor(tot, o, WAVE);
+              const int64_t first = p > c0 ? p : c0;
+              cend = first + tot;
+              if (cend < p + STEP || p + STEP >= e) break;  // the run ends in this step
+              p += STEP;
+#pragma unroll
+              for (int k = 0; k < W_LD; k++) a[k] = ncol4[(p >> 2) + W_GL * k + gl];
+            }
+            if (gl == 0) {
+              const int32_t vnext = row_at(A.ncol, cend, e);
+              D[sg] = make_int4((int)cend, (int)e, vnext, row_at(A.ncol, cend + 7, e));
+              atomicMin(&s_minz, vnext);
+            }
+            qi = qn;
+            dA = dB;
+            pA = pB;
+#pragma unroll
+            for (int k = 0; k < W_LD; k++) a[k] = bn[k];
+          }
+          __syncthreads();
         }
-        __syncthreads();
+      };
+      switch (kind) {
+        case 0: pass(std::integral_constant<int, 0>{}); break;
+        case 1: pass(std::integral_constant<int, 1>{}); break;
+        case 2: pass(std::integral_constant<int, 2>{}); break;
+        default: pass(std::integral_constant<int, 3>{}); break;
       }
       // clear the counters; the next window starts at the word of the
       // smallest value a cursor points at
