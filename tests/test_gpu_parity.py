@@ -193,6 +193,30 @@ def test_serial_and_overlapped_stages_agree(ctx):
             assert sa[k] == sb[k], k
 
 
+def test_caller_stream_and_tuning_bounds(ctx):
+    # device tensors on a side torch stream: the count is ordered on that
+    # stream (the 4-cycle stage forks from it and joins back into it)
+    import torch
+    import paper_2607_12074_amd as m4
+    g = gg.rmat(15, 10, 0.57, 0.19, 0.19, 31)
+    ref = oracle.closure(*g)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        rp = torch.from_numpy(g[0]).cuda()
+        col = torch.from_numpy(g[1]).cuda()
+        for _ in range(2):
+            assert ctx.count(rp, col) == ref
+    side.synchronize()
+    # out-of-range thresholds are rejected and leave the tuning unchanged
+    before = ctx.get_tuning()
+    for bad in ({"c4_med_max": 20000}, {"c4_med_win": -1}, {"probe_w": 0},
+                {"tri_wave_max": 65}, {"hub_min": 2}):
+        with pytest.raises(m4.M4Error) as e:
+            ctx.set_tuning(**bad)
+        assert e.value.code == m4.M4_EINVAL
+    assert ctx.get_tuning() == before
+
+
 def test_device_tensor_input(ctx):
     import torch
     g = gg.rmat(12, 10, 0.57, 0.19, 0.19, 8)
