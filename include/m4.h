@@ -37,7 +37,7 @@ typedef enum {
   M4_OK = 0,
   M4_EINVAL = 1,    /* bad argument, or a CSR that is not simple/symmetric/
                        sorted (detected only with M4_VALIDATE)               */
-  M4_ERANGE = 2,    /* n >= 2^31, nnz >= 2^31, or nnz != row_ptr[n]          */
+  M4_ERANGE = 2,    /* n >= 2^31, nnz > 2^31 - 1024, or nnz != row_ptr[n]   */
   M4_EOVERFLOW = 3, /* a count, or an intermediate sum, is >= 2^64          */
   M4_ENOMEM = 4,    /* device or pinned host allocation failed, or the
                        device budget cannot hold even one partition        */

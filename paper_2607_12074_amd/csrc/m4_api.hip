@@ -183,7 +183,8 @@ namespace m4 {
 int check_csr_args(const m4_csr* g) {
   if (!g) return M4_EINVAL;
   if (g->n < 0 || g->nnz < 0) return M4_EINVAL;
-  if (g->n >= (int64_t(1) << 31) || g->nnz >= (int64_t(1) << 31)) return M4_ERANGE;
+  // column positions (plus the row slack of aligned loads) must fit 32 bits
+  if (g->n >= (int64_t(1) << 31) || g->nnz > (int64_t(1) << 31) - 1024) return M4_ERANGE;
   if (g->nnz % 2) return M4_EINVAL;
   if (!g->row_ptr) return M4_EINVAL;
   if (g->nnz > 0 && !g->col) return M4_EINVAL;

@@ -580,7 +580,8 @@ __device__ __forceinline__ int short_visit(const C4Args& A, const int4* __restri
 // first takes whole segments by itself (an empty visit costs nothing for
 // descriptors held in registers, a short one five 16-byte loads); longer
 // visits are queued in LDS and walked by 8-lane groups, 64 entries (two
-// 16-byte loads per lane) per step, with the next queued segment's first
+// 16-byte loads per lane) per step, the next step's loads issued before a
+// step is counted, and the next queued segment's first
 // step in flight.  The next window starts at the smallest value any cursor
 // points at, so windows without endpoints are never visited.
 __global__ __launch_bounds__(W_NT) void k_c4_window(C4Args A) {
@@ -701,39 +702,55 @@ __global__ __launch_bounds__(W_NT) void k_c4_window(C4Args A) {
 #pragma unroll
             for (int k = 0; k < W_LD; k++)
               bn[k] = qn < nq ? ncol4[(pB >> 2) + W_GL * k + gl] : make_int4(0, 0, 0, 0);
-            const int64_t c0 = dA.x, e = dA.y;
-            int64_t p = pA;
-            int64_t cend = c0;  // new cursor
+            // positions fit 32 bits: the column array holds < 2^31 - 1024 entries
+            const int32_t c0 = dA.x, e = dA.y;
+            int32_t p = (int32_t)pA;
+            int32_t cend = c0;  // new cursor
             for (;;) {
+              // the next step's loads go out before this step's counting
+              const bool more = p + STEP < e;
+              int4 nx[W_LD];
+#pragma unroll
+              for (int k = 0; k < W_LD; k++)
+                nx[k] = more ? ncol4[((p + STEP) >> 2) + W_GL * k + gl] : make_int4(0, 0, 0, 0);
               int mine = 0;
-              uint64_t part = 0;  // < 4 W_LD counts of < 2^32 each
-              // the step's entries from the cursor on and before the row end
-              const int lo_o = (int)(c0 > p ? c0 - p : 0);
-              const int hi_o = (int)(e - p < STEP ? e - p : STEP);
+              // counts of one-zone windows of 4- or 8-bit counters sum below
+              // 2^32 over a step; wider ones need 64 bits
+              std::conditional_t<(KIND <= 1), uint32_t, uint64_t> part = 0;
+              // the step's entries from the cursor on and before the row end,
+              // as a bit mask over this lane's 4 W_LD entries
+              const int lo_o = c0 > p ? c0 - p : 0;
+              const int hi_o = e - p < STEP ? e - p : STEP;
+              uint32_t pm = 0;
+#pragma unroll
+              for (int k = 0; k < W_LD; k++) {
+                const int b = 4 * (W_GL * k + gl);
+                const int lk = min(max(lo_o - b, 0), 4), hk = min(max(hi_o - b, 0), 4);
+                pm |= ((1u << hk) - (1u << lk)) << (4 * k);  // lo_o <= hi_o, so lk <= hk
+              }
 #pragma unroll
               for (int k = 0; k < W_LD; k++)
 #pragma unroll
                 for (int r = 0; r < 4; r++) {
                   const int32_t xv = comp(a[k], r);
-                  const int o = 4 * (W_GL * k + gl) + r;
-                  if (o >= lo_o && o < hi_o && xv < hi) {
+                  if (((pm >> (4 * k + r)) & 1u) && xv < hi) {
                     part += window_inc_k<KIND>(A, cnt, wlo, base, xv);
                     mine++;
                   }
                 }
-              acc += part;
+              acc += (uint64_t)part;
               wedges += (unsigned long long)mine;
               // entries in the window form a run from the cursor: its length is
               // the group's total
               int tot = mine;
 #pragma unroll
               for (int o = 1; o < W_GL; o <<= 1) tot += __shfl_xor(tot, o, WAVE);
-              const int64_t first = p > c0 ? p : c0;
+              const int32_t first = p > c0 ? p : c0;
               cend = first + tot;
-              if (cend < p + STEP || p + STEP >= e) break;  // the run ends in this step
+              if (cend < p + STEP || !more) break;  // the run ends in this step
               p += STEP;
 #pragma unroll
-              for (int k = 0; k < W_LD; k++) a[k] = ncol4[(p >> 2) + W_GL * k + gl];
+              for (int k = 0; k < W_LD; k++) a[k] = nx[k];
             }
             if (gl == 0) {
               const int32_t vnext = row_at(A.ncol, cend, e);
