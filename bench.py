@@ -365,15 +365,39 @@ def main():
     torch.cuda.synchronize()
     note("warmup done")
 
-    # timed region: K full counts
+    # timed region: K full counts (each ends with its 48-byte result on the
+    # host, so the per-step wall times are complete counts)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    step_ms = []
     for _ in range(args.steps):
+        ts = time.perf_counter()
         counts = ctx.count(rp_d, col_d, flags=step_flags)
+        step_ms.append((time.perf_counter() - ts) * 1e3)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / max(args.steps, 1)
     note(f"timed {args.steps} steps: {ms_step:.3f} ms/step")
+
+    # outside the timed region: the same count from host arrays (the CSR
+    # copied over PCIe in the call), and a plain device copy for the
+    # achievable HBM rate on this machine
+    ts = time.perf_counter()
+    c_h = ctx.count(rp, col, flags=step_flags)
+    ms_host = (time.perf_counter() - ts) * 1e3
+    assert c_h == counts
+    buf_a = torch.empty(1 << 28, dtype=torch.int32, device=dev)
+    buf_b = torch.empty_like(buf_a)
+    buf_a.fill_(1)
+    buf_b.copy_(buf_a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        buf_b.copy_(buf_a)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbps = 5 * 2 * (1 << 30) / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del buf_a, buf_b
 
     # kernel durations: K more counts with the stages on one stream, so that
     # each kernel's HIP events (recorded on its launch stream) time it alone
@@ -409,10 +433,19 @@ def main():
         ref = oracle.closure(rp, col, threads=0)
         cpu_s = time.perf_counter() - t0
         parity = (tuple(ref) == tuple(counts))
+        model = ""
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
         cpu = {"value": m / cpu_s, "unit": "edges/s", "cores": oracle.threads(0),
                "kind": "oracle",
                "sample": f"whole workload graph (n={n}, m={m}), plain closure counter, "
-                         f"{cpu_s:.1f} s"}
+                         f"{cpu_s:.1f} s",
+               "cpu_model": model}
         note(f"cpu oracle: {cpu_s:.1f} s, parity {parity}")
 
     batched = run_batch_leg(ctx, args) if args.batch_graphs > 0 else None
@@ -431,7 +464,11 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
+        "ms_per_step_median": float(np.median(step_ms)) if step_ms else None,
+        "ms_per_step_min": float(np.min(step_ms)) if step_ms else None,
         "ms_per_step_stages_serial": ms_step_serial,
+        "pcie_inclusive": {"ms": ms_host, "edges_per_s": m / (ms_host * 1e-3),
+                           "note": "host CSR copied to the device inside the call"},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -446,7 +483,8 @@ def main():
         "parity_vs_oracle": parity,
         "roofline": {"bound": "hbm", "kernel": KERNEL_SYMBOL[dname], "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "alg_bytes": B, "ms": float(ms_k[dom])},
+                     "traffic": traffic, "alg_bytes": B, "ms": float(ms_k[dom]),
+                     "measured_copy_GBps": copy_gbps},
         "kernels": {names[i]: {"ms": round(float(ms_k[i]), 4), "elems": st["k_elems"][i],
                                "rows": st["k_rows"][i], "aux": st["k_aux"][i],
                                "aux2": st["k_aux2"][i],
