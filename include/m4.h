@@ -94,7 +94,7 @@ enum {
   M4_K_TRI_512,       /* ... (256, 512]                                        */
   M4_K_TRI_256,       /* ... (128, 256]                                        */
   M4_K_TRI_128,       /* ... (wave max, 128]                                   */
-  M4_K_TRI_WAVE,      /* ... out-degree <= 64, one wavefront per owner         */
+  M4_K_TRI_WAVE,      /* ... out-degree <= tri_wave_max, one wavefront each    */
   M4_K_C4_PLAN,       /* 4-cycle wedge bounds and owner buckets                 */
   M4_K_C4_WINDOW,     /* 4-cycle owners with windows of dense LDS counters     */
   M4_K_C4_MED,        /* ... medium wedge bound, 16384-slot LDS hash table     */
@@ -114,7 +114,9 @@ enum {
  *                   the triangles (u, v, w), u < v < w, of |N+(w)|
  *   4-cycle slots:  k_elems = wedge endpoints counted, k_rows = owners,
  *                   k_aux = lower neighbours (segments), k_aux2 = segment
- *                   visits (window slots) or row entries read (hash slot)
+ *                   visits (window slot) or row entries read (table slots;
+ *                   an owner counted in rank ranges reads its rows once per
+ *                   pass)
  *   closure:        k_elems = oriented edges, k_rows = vertices
  *   build:          k_elems = CSR entries, k_rows = vertices */
 typedef struct {
@@ -131,6 +133,9 @@ typedef struct {
   uint64_t halo_rows;       /* rows copied as halo over all partitions           */
   uint64_t k_elems[M4_NK], k_rows[M4_NK], k_aux[M4_NK], k_aux2[M4_NK];
   double ms_kernel[M4_NK];  /* per-slot kernel time (M4_TIMING)                  */
+  /* stage times (M4_TIMING): ms_tri runs from the end of the build to the end
+   * of the triangle stage, ms_c4 from there to the end of both anchor stages
+   * (the two overlap unless M4_SERIAL) */
   double ms_total, ms_build, ms_tri, ms_c4, ms_closure, ms_h2d;
 } m4_stats;
 
