@@ -88,3 +88,24 @@ def test_web_rmat_under_budget(ctx):
     assert st["partitions"] >= 3 and st["h2d_bytes"] > 0
     for k in ("T", "K4", "C4_ni", "D_ni"):
         assert st[k] == rst[k], k
+
+
+def test_partition_with_ranged_medium_table(ctx):
+    # owners with wedge bounds in (12288, 65536] counted over rank ranges of
+    # the medium table (c4_med_win=1 sends all of them there), on stored row
+    # prefixes of a partition
+    import paper_2607_12074_amd as m4
+    g = gg.rmat(16, 12, 0.57, 0.19, 0.19, 21)
+    saved = ctx.get_tuning()
+    try:
+        ctx.set_tuning(c4_med_win=1)
+        ref, rst = ctx.count(*g, stats=True)
+        assert ref == oracle.closure(*g)
+        got, st = ctx.count(*g, flags=m4.M4_FORCE_PARTITION | m4.M4_STATS,
+                            budget=budget_for(g, 4), stats=True)
+        assert got == ref
+        assert st["partitions"] >= 3
+        for k in ("C4_ni", "wedges"):
+            assert st[k] == rst[k], k
+    finally:
+        ctx.set_tuning(**saved)
