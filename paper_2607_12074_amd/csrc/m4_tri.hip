@@ -26,8 +26,12 @@ namespace m4 {
 
 namespace {
 
+// At least 5 wavefronts per SIMD: the register cap (<= 96 VGPRs) trades a few
+// spills for a fifth resident wavefront, which hides more of the load and
+// probe latency of the owners whose LDS footprint allows it (out-degree up
+// to 256); the larger owners are bound by LDS either way.
 template <int KMAX, int NT>
-__global__ __launch_bounds__(NT) void k_tri_lds(TriArgs A) {
+__global__ __launch_bounds__(NT, 5) void k_tri_lds(TriArgs A) {
   constexpr int WMAX = (KMAX + 63) / 64;
   constexpr bool HASH = KMAX <= 512;  // the hash table fits beside the bitmap
   constexpr int HSLOTS = HASH ? 2 * KMAX : 1;
