@@ -68,3 +68,14 @@ def test_signature_keys_distinguish_masks():
                 keys[k] = (j, mp, mm)
     assert f(2, 5, 3, 0) != f(2, 5, 1, 2)  # adjacent to both vs to exactly one
     assert f(2, 5, 3, 0) != f(2, 6, 3, 0)
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    # no fallback: without the built HIP library every call raises
+    import paper_2607_12074_amd as m4
+    monkeypatch.setattr(m4, "LIB_PATH", "/nonexistent/libm4.so")
+    monkeypatch.setattr(m4, "_lib", None)
+    with pytest.raises(m4.M4Error) as e:
+        m4.lib()
+    assert e.value.code == m4.M4_EDEVICE
+    assert "missing" in str(e.value)
