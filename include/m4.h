@@ -110,8 +110,9 @@ enum {
  * needs M4_TIMING.  Per slot:
  *   triangle slots: k_elems = sum of |N+(v)| over the owners' out-neighbours
  *                   v (elements a scanning intersection reads), k_rows = owners,
- *                   k_aux = out-list entries of the owners, k_aux2 = sum over
- *                   the triangles (u, v, w), u < v < w, of |N+(w)|
+ *                   k_aux = out-list entries of the owners, k_aux2 = 4-byte
+ *                   words the kernel read from out-lists and hub tables (one
+ *                   per scanned element, two per 8-byte table slot probed)
  *   4-cycle slots:  k_elems = wedge endpoints counted, k_rows = owners,
  *                   k_aux = lower neighbours (segments), k_aux2 = segment
  *                   visits (window slot) or row entries read (table slots;
@@ -137,6 +138,11 @@ typedef struct {
    * of the triangle stage, ms_c4 from there to the end of both anchor stages
    * (the two overlap unless M4_SERIAL) */
   double ms_total, ms_build, ms_tri, ms_c4, ms_closure, ms_h2d;
+  /* device memory the context held when the call returned: its workspaces at
+   * their largest for this call (the footprint of the call).  Under a device
+   * budget it never exceeds device_budget_bytes: the call first frees the
+   * workspaces of earlier unbudgeted calls and allocates exactly the budget. */
+  uint64_t device_bytes;
 } m4_stats;
 
 typedef struct m4_ctx m4_ctx;

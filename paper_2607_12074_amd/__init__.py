@@ -59,7 +59,8 @@ class Stats(ctypes.Structure):
                 ("ms_kernel", ctypes.c_double * M4_NK),
                 ("ms_total", ctypes.c_double), ("ms_build", ctypes.c_double),
                 ("ms_tri", ctypes.c_double), ("ms_c4", ctypes.c_double),
-                ("ms_closure", ctypes.c_double), ("ms_h2d", ctypes.c_double)]
+                ("ms_closure", ctypes.c_double), ("ms_h2d", ctypes.c_double),
+                ("device_bytes", ctypes.c_uint64)]
 
     def to_dict(self):
         d = {k: int(v) for k, v in zip(BASIS, self.basis)}

@@ -17,15 +17,15 @@ using namespace m4;
 
 namespace m4 {
 
-void DevBuf::ensure(size_t bytes, hipStream_t s) {
-  if (bytes <= cap) return;
+void DevBuf::ensure(size_t bytes, hipStream_t s, bool exact) {
+  if (exact ? bytes == cap : bytes <= cap) return;
   if (ptr) {
     M4_HIP(hipStreamSynchronize(s));
     M4_HIP(hipFree(ptr));
     ptr = nullptr;
     cap = 0;
   }
-  size_t want = bytes + bytes / 8 + (1 << 20);
+  size_t want = exact ? bytes : bytes + bytes / 8 + (1 << 20);
   hipError_t e = hipMalloc((void**)&ptr, want);
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -47,6 +47,30 @@ void DevBuf::release() {
 }
 
 static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+size_t batch_held_bytes(const m4_ctx* c);
+void batch_release(m4_ctx* c);
+
+}  // namespace m4
+
+size_t m4_ctx::held_bytes() const {
+  return prep.cap + tmp.cap + big.cap + big2.cap + input.cap + tout.cap + extra.cap +
+         m4::batch_held_bytes(this) + sizeof(m4::Scal);
+}
+
+void m4_ctx::release_resident() {
+  (void)hipStreamSynchronize(stream);
+  (void)hipStreamSynchronize(stream2);
+  prep.release();
+  tmp.release();
+  big.release();
+  big2.release();
+  input.release();
+  tout.release();
+  m4::batch_release(this);
+}
+
+namespace m4 {
 
 size_t prep_bytes(int64_t n, int64_t nnz) {
   size_t b = 0;
@@ -92,6 +116,14 @@ size_t c4_tmp_bytes(int64_t n) {
 int set_error(m4_ctx* ctx, int code, const std::string& msg) {
   if (ctx) ctx->last_error = msg;
   return code;
+}
+
+int scal_error(m4_ctx* ctx, int err) {
+  if (err & ERR_INVALID) return set_error(ctx, M4_EINVAL, "CSR is not simple, symmetric and sorted");
+  if (err & ERR_PROBE)
+    return set_error(ctx, M4_EINTERNAL, "an open-addressing probe ran past its table size");
+  if (err) return set_error(ctx, M4_EINTERNAL, "4-cycle range plan exceeded its bound");
+  return M4_OK;
 }
 
 }  // namespace m4
@@ -381,8 +413,7 @@ extern "C" int m4_count_motifs4_ex(m4_ctx* ctx, const m4_csr* g, const m4_opts* 
   M4_HIP(hipMemcpyAsync(ctx->scal_host, ctx->scal, sizeof(Scal), hipMemcpyDeviceToHost, s));
   M4_HIP(hipStreamSynchronize(s));
   const Scal& h = *ctx->scal_host;
-  if (h.err & 1) return set_error(ctx, M4_EINVAL, "CSR is not simple, symmetric and sorted");
-  if (h.err) return set_error(ctx, M4_EINTERNAL, "4-cycle range plan exceeded its bound");
+  if (h.err) return scal_error(ctx, h.err);
   if (h.status == 3) return set_error(ctx, M4_EOVERFLOW, "a count is >= 2^64");
   if (h.status != 0) return set_error(ctx, M4_EINTERNAL, "closure consistency check failed");
   for (int i = 0; i < 6; i++) out[i] = h.out[i];
@@ -394,6 +425,7 @@ extern "C" int m4_count_motifs4_ex(m4_ctx* ctx, const m4_csr* g, const m4_opts* 
     st->k_rows[M4_K_CLOSURE] = (uint64_t)g->n;
     st->partitions = 1;
     st->h2d_bytes = (uint64_t)h2d;
+    st->device_bytes = ctx->held_bytes();
     if (timing) {
       float ms = 0, mh = 0;
       (void)hipEventElapsedTime(&ms, ctx->ev[5], ctx->ev[4]);
@@ -445,7 +477,9 @@ extern "C" int m4_edge_triangles(m4_ctx* ctx, const m4_csr* g, const m4_opts* o,
   edge_t_to_input(P, rp, col, dst, s);
   if (!g->on_device)
     M4_HIP(hipMemcpyAsync(t_out, dst, (size_t)g->nnz * 4, hipMemcpyDeviceToHost, s));
+  M4_HIP(hipMemcpyAsync(ctx->scal_host, ctx->scal, sizeof(Scal), hipMemcpyDeviceToHost, s));
   M4_HIP(hipStreamSynchronize(s));
+  if (ctx->scal_host->err) return scal_error(ctx, ctx->scal_host->err);
   return M4_OK;
   M4_GUARD_END
 }

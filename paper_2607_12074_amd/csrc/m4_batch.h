@@ -16,7 +16,7 @@ struct BatchArgs {
   const int64_t* eoff;
   const int64_t* rowp;
   const int32_t* col;
-  const int32_t* order;
+  const int32_t* order;  // graphs in launch order (null: 0, 1, ..., norder - 1)
   int64_t norder;
   unsigned int* work;
   int32_t* perm;
@@ -33,16 +33,17 @@ struct BatchArgs {
   int light;
   uint32_t flags;
   uint32_t cache_rows;
-  int kbig;
-  uint64_t* gbits;
-  int32_t* garr;
+  int too_big;  // status of a graph the kernel leaves to another path
+  // vertices and CSR entries the work arrays hold: a graph whose offsets
+  // reach past them gets status M4_EINVAL and is not touched
+  int64_t vcap, ecap;
 };
 
 struct BatchPlan {
   int64_t G = 0, sum_n = 0, sum_nnz = 0;
   std::vector<int32_t> order;  // graphs for the fused kernel, largest first
   std::vector<int64_t> big;    // graphs for the single-graph path
-  int kbig = 0, variant = 0, grid = 1;
+  int variant = 0, grid = 1;
   size_t arena_bytes = 0, o_arena = 0;
   bool staged = false;
   BatchArgs args{};
@@ -50,13 +51,17 @@ struct BatchPlan {
 
 int batch_variant_kb(int variant);
 // true when graph (n, rp) is counted by the fused kernel rather than by the
-// single-graph path
+// single-graph path (the kernel applies the same test to the arena itself)
 bool batch_graph_fits(int64_t n, const int64_t* rp, int variant);
 void batch_prepare(m4_ctx* c, BatchBuffers& B, BatchPlan& P, int64_t G, const int64_t* hvoff,
-                   const int64_t* heoff, const int64_t* hrowp, const m4_batch* dev_arena,
-                   int variant, int light, uint32_t flags, uint32_t cache_rows, hipStream_t s);
+                   const int64_t* heoff, const m4_batch* dev_arena, int variant, int light,
+                   uint32_t flags, uint32_t cache_rows, hipStream_t s);
 void batch_stage(BatchBuffers& B, const BatchPlan& P, const int64_t* voff, const int64_t* eoff,
                  const int64_t* rowp, const int32_t* col);
 void batch_enqueue(BatchBuffers& B, const BatchPlan& P, hipStream_t s);
+// the fused kernel alone (1024 threads, 96 KiB of LDS tiles) on grid workgroups
+void batch_launch_fused(const BatchArgs& A, int grid, hipStream_t s);
+// largest wedge bound of the fused kernel's per-wavefront 4-cycle hash
+int batch_light_max();
 
 }  // namespace m4

@@ -40,6 +40,7 @@ __host__ __device__ constexpr int tri_lds_kmax() {
 
 constexpr int PW_TRI = 2560;  // per-wavefront triangle arrays (k <= 64)
 constexpr int PW_HASH = 512;  // per-wavefront hash slots of the light 4-cycle owners
+constexpr int64_t kBatchWorkMax = int64_t(1) << 26;  // sum of d^2 of a fused-kernel graph
 
 template <int NT>
 __device__ __forceinline__ void bitonic_u32(uint32_t* s, int P) {
@@ -70,8 +71,11 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs A) {
   __shared__ __align__(16) unsigned char U[UB];
   __shared__ int16_t rankL[B_NMAX];
   __shared__ int16_t dlist[B_NMAX];
-  __shared__ int s_item, s_r1, s_ndef, s_below;
+  __shared__ int s_item, s_r1, s_ndef, s_below, s_err;
+  __shared__ unsigned int s_dmax;
+  __shared__ unsigned long long s_d2;
   __shared__ U128 gacc[7];
+  constexpr int KB = tri_lds_kmax<UB>();
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
 
   for (;;) {
@@ -80,21 +84,56 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs A) {
     const int64_t item = s_item;
     __syncthreads();
     if (item >= A.norder) break;
-    const int64_t g = A.order[item];
-    const int64_t v0 = A.voff[g], e0 = A.eoff[g];
-    const int n = (int)(A.voff[g + 1] - v0);
-    const int64_t nnz = A.eoff[g + 1] - e0;
+    const int64_t g = A.order ? A.order[item] : item;
+    const int64_t v0 = A.voff[g], e0 = A.eoff[g], v1 = A.voff[g + 1], e1 = A.eoff[g + 1];
     unsigned long long* outg = A.out + 6 * g;
+    // the graph's slices of the work arrays must lie inside them
+    if (v0 < 0 || e0 < 0 || v1 < v0 || e1 < e0 || v1 > A.vcap || e1 > A.ecap || (e1 - e0) % 2) {
+      if (tid == 0) A.status[g] = M4_EINVAL;
+      continue;
+    }
+    const int64_t nn = v1 - v0;
+    const int n = nn > B_NMAX ? B_NMAX + 1 : (int)nn;
+    const int64_t nnz = e1 - e0;
     if (n < 4 || nnz == 0) {
       if (tid < 6) outg[tid] = 0;
       if (tid == 0) A.status[g] = 0;
       continue;
     }
     if (n > B_NMAX) {
-      if (tid == 0) A.status[g] = B_TOO_BIG;
+      if (tid == 0) A.status[g] = A.too_big;
       continue;
     }
     const int64_t* rp = A.rowp + v0 + g;
+    // The graph is counted here only when every per-owner structure fits the
+    // workgroup's LDS (out-degree <= KB) and its work is modest; this is
+    // decided from the arena's contents on every launch, so a replayed launch
+    // never trusts an earlier routing.  Other graphs are left to the
+    // single-graph path (status B_TOO_BIG).
+    if (tid == 0) {
+      s_dmax = 0;
+      s_d2 = 0;
+      s_err = 0;
+    }
+    __syncthreads();
+    {
+      unsigned int dm = 0;
+      unsigned long long d2 = 0;
+      for (int v = tid; v < n; v += NT) {
+        const int64_t d = rp[v + 1] - rp[v];
+        const unsigned int du = d < 0 ? 0xffffffffu : (d > 0x7fffffff ? 0x7fffffffu : (unsigned)d);
+        dm = du > dm ? du : dm;
+        d2 += (unsigned long long)du * du;
+      }
+      if (dm) atomicMax(&s_dmax, dm);
+      if (d2) atomicAdd(&s_d2, d2);
+    }
+    __syncthreads();
+    if (s_dmax > (unsigned)KB || s_dmax >= (unsigned)n || s_d2 > (unsigned long long)kBatchWorkMax ||
+        rp[0] != 0 || rp[n] != nnz) {
+      if (tid == 0) A.status[g] = A.too_big;
+      continue;
+    }
     const int32_t* cl = A.col + e0;
     int32_t* perm = A.perm + v0;
     int32_t* dr = A.dr + v0;
@@ -217,6 +256,7 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs A) {
     T.t = t;
     T.flags = A.flags;
     T.cache_rows = A.cache_rows;
+    T.err = &s_err;
     u128_t k4 = 0;
     unsigned long long st0 = 0, st1 = 0, st2 = 0, st3 = 0, st4 = 0, st5 = 0;
     {
@@ -307,17 +347,26 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs A) {
             const int si = upper_index(spref, nc, q);
             const int32_t x = ncol[sst[si] + (q - spref[si])];
             if (x < r1 || x >= r) continue;
+            // at most wb <= S / 2 distinct keys: x or a free slot within S probes
             uint32_t h = ((uint32_t)x * 0x9E3779B1u) >> shift;
-            for (;;) {
+            bool found = false;
+            for (int probes = 0; probes < S; probes++) {
               const int32_t kk = hkey[h];
-              if (kk == x) break;
+              if (kk == x) {
+                found = true;
+                break;
+              }
               if (kk == -1) {
                 const int32_t prev = atomicCAS(&hkey[h], -1, x);
-                if (prev == -1 || prev == x) break;
+                if (prev == -1 || prev == x) {
+                  found = true;
+                  break;
+                }
               }
               h = (h + 1) & mask;
             }
-            c4 += atomicAdd(&hcnt[h], 1u);
+            if (found) c4 += atomicAdd(&hcnt[h], 1u);
+            else atomicOr(&s_err, ERR_PROBE);
           }
           wave_sync();
         }
@@ -379,7 +428,8 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs A) {
       u128_t in[7];
       for (int i = 0; i < 7; i++) in[i] = load_u128(&gacc[i]);
       unsigned long long res[6], bas[8];
-      A.status[g] = finalize_basis(in, res, bas);
+      const int fs = finalize_basis(in, res, bas);
+      A.status[g] = s_err ? 7 : fs;
       for (int i = 0; i < 6; i++) outg[i] = res[i];
       if (A.basis)
         for (int i = 0; i < 8; i++) A.basis[8 * g + i] = bas[i];
@@ -398,7 +448,6 @@ static size_t al(size_t b) { return (b + 255) & ~size_t(255); }
 
 void BatchBuffers::release() {
   dev.release();
-  gscratch.release();
   if (h_out) (void)hipHostFree(h_out);
   if (h_status) (void)hipHostFree(h_status);
   if (h_stage) (void)hipHostFree(h_stage);
@@ -407,8 +456,6 @@ void BatchBuffers::release() {
   h_stage = nullptr;
   h_out_cap = h_stage_cap = 0;
 }
-
-constexpr int64_t kBatchWorkMax = int64_t(1) << 26;  // sum of d^2 of a fused-kernel graph
 
 int batch_variant_kb(int variant) {
   return variant == 1 ? tri_lds_kmax<40960>() : tri_lds_kmax<98304>();
@@ -426,31 +473,29 @@ bool batch_graph_fits(int64_t n, const int64_t* rp, int variant) {
   return d2 <= kBatchWorkMax;
 }
 
-// Plans a launch over an arena whose offsets (and row pointers, for the
-// largest degree) are readable on the host, and lays out the device buffers.
+// Plans a launch over an arena whose offsets are readable on the host, and
+// lays out the device buffers.  The plan depends on the offsets only: a graph
+// with more than B_NMAX vertices goes to the single-graph path at once, every
+// other one is queued for the fused kernel (largest first), which itself
+// checks the graph's degrees and work against its LDS structures on every
+// launch.
 // dev_arena: device pointers of the arena, or null to stage the host arena
 // into pinned memory and upload it within the launch.
 void batch_prepare(m4_ctx* c, BatchBuffers& B, BatchPlan& P, int64_t G, const int64_t* hvoff,
-                   const int64_t* heoff, const int64_t* hrowp, const m4_batch* dev_arena,
-                   int variant, int light, uint32_t flags, uint32_t cache_rows, hipStream_t s) {
+                   const int64_t* heoff, const m4_batch* dev_arena, int variant, int light,
+                   uint32_t flags, uint32_t cache_rows, hipStream_t s) {
   const int64_t sum_n = hvoff[G], sum_nnz = heoff[G];
-  // A graph goes to the fused kernel when one workgroup's LDS holds it and its
-  // work is modest; more vertices, out-lists beyond the LDS bitmap, or a large
-  // sum of squared degrees send it to the single-graph path over all CUs.
   std::vector<int64_t> nnz(G);
   P.order.clear();
   P.big.clear();
   for (int64_t g = 0; g < G; g++) {
     nnz[g] = heoff[g + 1] - heoff[g];
-    if (batch_graph_fits(hvoff[g + 1] - hvoff[g], hrowp + hvoff[g] + g, variant))
-      P.order.push_back((int32_t)g);
-    else
-      P.big.push_back(g);
+    if (hvoff[g + 1] - hvoff[g] <= B_NMAX) P.order.push_back((int32_t)g);
+    else P.big.push_back(g);
   }
   // largest graphs first
   std::stable_sort(P.order.begin(), P.order.end(),
                    [&](int32_t x, int32_t y) { return nnz[x] > nnz[y]; });
-  P.kbig = 0;
   P.variant = variant;
   P.G = G;
   P.sum_n = sum_n;
@@ -475,10 +520,6 @@ void batch_prepare(m4_ctx* c, BatchBuffers& B, BatchPlan& P, int64_t G, const in
   if (P.staged) P.o_arena = add(P.arena_bytes);
   B.dev.ensure(need, s);
   char* d = B.dev.ptr;
-  if (P.kbig) {
-    size_t K = P.kbig, WK = (K + 63) / 64;
-    B.gscratch.ensure((size_t)grid * (K * WK * 8 + (7 * K + 2) * 4) + 512, s);
-  }
   if (B.h_out_cap < (size_t)G) {
     if (B.h_out) (void)hipHostFree(B.h_out);
     if (B.h_status) (void)hipHostFree(B.h_status);
@@ -494,8 +535,9 @@ void batch_prepare(m4_ctx* c, BatchBuffers& B, BatchPlan& P, int64_t G, const in
     M4_HIP(hipHostMalloc((void**)&B.h_stage, P.arena_bytes, hipHostMallocDefault));
     B.h_stage_cap = P.arena_bytes;
   }
-  M4_HIP(hipMemcpyAsync(d + o_order, P.order.data(), P.order.size() * 4 + 4,
-                        hipMemcpyHostToDevice, s));
+  if (!P.order.empty())
+    M4_HIP(hipMemcpyAsync(d + o_order, P.order.data(), P.order.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice, s));
   BatchArgs& A = P.args;
   A = BatchArgs{};
   A.G = G;
@@ -527,12 +569,9 @@ void batch_prepare(m4_ctx* c, BatchBuffers& B, BatchPlan& P, int64_t G, const in
   A.light = light;
   A.flags = flags;
   A.cache_rows = cache_rows;
-  A.kbig = P.kbig;
-  if (P.kbig) {
-    size_t K = P.kbig, WK = (K + 63) / 64;
-    A.gbits = reinterpret_cast<uint64_t*>(B.gscratch.ptr);
-    A.garr = reinterpret_cast<int32_t*>(B.gscratch.ptr + al((size_t)grid * K * WK * 8));
-  }
+  A.too_big = B_TOO_BIG;
+  A.vcap = sum_n;
+  A.ecap = sum_nnz;
 }
 
 // Copies a host arena into the pinned staging buffer of a prepared plan.
@@ -555,16 +594,29 @@ void batch_enqueue(BatchBuffers& B, const BatchPlan& P, hipStream_t s) {
                           s));
   k_batch_reset<<<1, 1, 0, s>>>(A.work);
   fill_u32(A.status, (uint32_t)B_TOO_BIG, (size_t)P.G, s);
-  if (P.variant == 1)
-    k_batch<512, 40960><<<P.grid, 512, 0, s>>>(A);
-  else
-    k_batch<1024, 98304><<<P.grid, 1024, 0, s>>>(A);
+  if (A.norder > 0) {
+    if (P.variant == 1)
+      k_batch<512, 40960><<<P.grid, 512, 0, s>>>(A);
+    else
+      k_batch<1024, 98304><<<P.grid, 1024, 0, s>>>(A);
+  }
   M4_HIP(hipMemcpyAsync(B.h_out, A.out, P.G * 48, hipMemcpyDeviceToHost, s));
   M4_HIP(hipMemcpyAsync(B.h_status, A.status, P.G * 4, hipMemcpyDeviceToHost, s));
 }
 
+// The captured launch of the last arena.  It is replayed only when the new
+// arena has the same offsets (compared by content) and, for a device arena,
+// the same device pointers (they are baked into the captured kernel
+// arguments); the arena's rows and columns may differ freely, because the
+// kernel decides per launch which graphs it counts.
+void batch_launch_fused(const BatchArgs& A, int grid, hipStream_t s) {
+  k_batch<1024, 98304><<<grid, 1024, 0, s>>>(A);
+}
+
+int batch_light_max() { return PW_HASH / 2; }
+
 struct BatchState {
-  int64_t G = -1, sum_n = 0, sum_nnz = 0;
+  std::vector<int64_t> voff, eoff;
   const void* key[4] = {nullptr, nullptr, nullptr, nullptr};
   int variant = -1, light = -1;
   uint32_t flags = 0, cache_rows = 0;
@@ -586,6 +638,10 @@ struct BatchState {
     buf.release();
   }
 };
+
+size_t batch_held_bytes(const m4_ctx* c) { return c->batch ? c->batch->buf.dev.cap : 0; }
+
+void batch_release(m4_ctx* c) { destroy_batch_state(c); }
 
 void destroy_batch_state(m4_ctx* c) {
   delete c->batch;
@@ -625,7 +681,7 @@ int count_batch_impl(m4_ctx* c, const m4_batch* b, const m4_opts* o, uint64_t* o
     hvoff = b->voff;
     heoff = b->eoff;
   }
-  const int64_t sum_n = hvoff[G], sum_nnz = heoff[G];
+  const int64_t sum_nnz = heoff[G];
   if (hvoff[0] != 0 || heoff[0] != 0 || sum_nnz >= (int64_t(1) << 31))
     return set_error(c, M4_ERANGE, "batch offsets out of range");
   for (int64_t g = 0; g < G; g++)
@@ -661,32 +717,25 @@ int count_batch_impl(m4_ctx* c, const m4_batch* b, const m4_opts* o, uint64_t* o
     return rc;
   }
 
-  const bool same = S.G == G && S.sum_n == sum_n && S.sum_nnz == sum_nnz &&
-                    S.key[0] == b->voff && S.key[1] == b->eoff && S.key[2] == b->row_ptr &&
-                    S.key[3] == b->col && S.variant == variant && S.light == light &&
-                    S.flags == flags && S.cache_rows == cache_rows &&
-                    S.on_device == (b->on_device != 0) && S.stream == s && S.exec;
+  const bool dev_same = !b->on_device || (S.key[0] == b->voff && S.key[1] == b->eoff &&
+                                           S.key[2] == b->row_ptr && S.key[3] == b->col);
+  const bool same = S.exec && dev_same && S.voff.size() == (size_t)(G + 1) &&
+                    memcmp(S.voff.data(), hvoff, (G + 1) * 8) == 0 &&
+                    memcmp(S.eoff.data(), heoff, (G + 1) * 8) == 0 && S.variant == variant &&
+                    S.light == light && S.flags == flags && S.cache_rows == cache_rows &&
+                    S.on_device == (b->on_device != 0) && S.stream == s;
   if (!same) {
     S.drop_graph();
-    std::vector<int64_t> hrp;
-    const int64_t* rpp = b->row_ptr;
-    if (b->on_device) {
-      hrp.resize(sum_n + G);
-      M4_HIP(hipMemcpyAsync(hrp.data(), b->row_ptr, (sum_n + G) * 8, hipMemcpyDeviceToHost, s));
-      M4_HIP(hipStreamSynchronize(s));
-      rpp = hrp.data();
-    }
-    batch_prepare(c, S.buf, S.plan, G, hvoff, heoff, rpp, b->on_device ? b : nullptr, variant,
-                  light, flags, cache_rows, s);
-    // capture the whole launch once; later calls on this arena replay it
+    batch_prepare(c, S.buf, S.plan, G, hvoff, heoff, b->on_device ? b : nullptr, variant, light,
+                  flags, cache_rows, s);
+    // capture the whole launch once; later calls on this layout replay it
     M4_HIP(hipStreamSynchronize(s));
     M4_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     batch_enqueue(S.buf, S.plan, s);
     M4_HIP(hipStreamEndCapture(s, &S.graph));
     M4_HIP(hipGraphInstantiate(&S.exec, S.graph, nullptr, nullptr, 0));
-    S.G = G;
-    S.sum_n = sum_n;
-    S.sum_nnz = sum_nnz;
+    S.voff.assign(hvoff, hvoff + G + 1);
+    S.eoff.assign(heoff, heoff + G + 1);
     S.key[0] = b->voff;
     S.key[1] = b->eoff;
     S.key[2] = b->row_ptr;
@@ -704,16 +753,20 @@ int count_batch_impl(m4_ctx* c, const m4_batch* b, const m4_opts* o, uint64_t* o
   if (timing) M4_HIP(hipEventRecord(e1, s));
   M4_HIP(hipStreamSynchronize(s));
   int rc = M4_OK;
+  std::vector<int64_t> single;
   for (int64_t g = 0; g < G; g++) {
     const int sg = S.buf.h_status[g];
-    if (sg == B_TOO_BIG) continue;
+    if (sg == B_TOO_BIG) {
+      single.push_back(g);
+      continue;
+    }
     if (sg == 3 && rc == M4_OK) rc = set_error(c, M4_EOVERFLOW, "a count is >= 2^64");
     if (sg != 0 && sg != 3 && rc == M4_OK)
-      rc = set_error(c, M4_EINTERNAL, "closure consistency check failed");
+      rc = set_error(c, M4_EINTERNAL, "closure consistency or probe bound check failed");
     memcpy(out + 6 * g, S.buf.h_out + 6 * g, 48);
   }
-  // graphs beyond one workgroup: the multi-kernel single-graph path
-  for (int64_t g : S.plan.big) {
+  // graphs the fused kernel left alone: the multi-kernel single-graph path
+  for (int64_t g : single) {
     m4_csr sub;
     sub.n = hvoff[g + 1] - hvoff[g];
     sub.nnz = heoff[g + 1] - heoff[g];

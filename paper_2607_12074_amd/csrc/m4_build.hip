@@ -64,7 +64,7 @@ __global__ void k_validate_rows(const int64_t* __restrict__ rp, int64_t n, int64
   if (v == 0 && rp[0] != 0) bad = true;
   if (v == n && rp[n] != nnz) bad = true;
   if (v < n && rp[v + 1] < rp[v]) bad = true;
-  if (bad) atomicOr(&scal->err, 1);
+  if (bad) atomicOr(&scal->err, ERR_INVALID);
 }
 
 __global__ void k_validate_entries(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
@@ -78,7 +78,7 @@ __global__ void k_validate_entries(const int64_t* __restrict__ rp, const int32_t
     int64_t lo = rp[x], hi = rp[x + 1];
     bad = lo >= hi || !has(col, lo, hi - 1, (int32_t)v);
   }
-  if (bad) atomicOr(&scal->err, 1);
+  if (bad) atomicOr(&scal->err, ERR_INVALID);
 }
 
 __global__ void k_identity(int32_t* __restrict__ p, uint32_t* __restrict__ k, int64_t n) {

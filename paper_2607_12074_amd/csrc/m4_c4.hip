@@ -281,16 +281,29 @@ __global__ __launch_bounds__(NT) void k_c4_hash(C4Args A) {
       owners++;
       segs += (unsigned long long)nl;
     }
+    // at most 3/4 S distinct keys: every probe meets x or a free slot within
+    // S steps (a longer one means a broken bound and is reported, not spun)
     auto insert = [&](int32_t x) {
       uint32_t h = ((uint32_t)x * 0x9E3779B1u) >> shift;
-      for (;;) {
+      bool ok = false;
+      for (int probes = 0; probes < S; probes++) {
         const int32_t k = hkey[h];
-        if (k == x) break;
+        if (k == x) {
+          ok = true;
+          break;
+        }
         if (k == -1) {
           const int32_t prev = atomicCAS(&hkey[h], -1, x);
-          if (prev == -1 || prev == x) break;
+          if (prev == -1 || prev == x) {
+            ok = true;
+            break;
+          }
         }
         h = (h + 1) & mask;
+      }
+      if (!ok) {
+        atomicOr(&A.scal->err, ERR_PROBE);
+        return;
       }
       acc += atomicAdd(&hcnt[h], 1u);
       wedges++;
@@ -348,7 +361,7 @@ __global__ __launch_bounds__(NT) void k_c4_hash(C4Args A) {
           if (s_rng[nr] >= u) break;
         }
         if (s_rng[nr] < u) {  // more ranges than planned for: not counted
-          atomicOr(&A.scal->err, 2);
+          atomicOr(&A.scal->err, ERR_RANGES);
           nr = 0;
         }
         s_nr = nr;

@@ -7,10 +7,13 @@
 namespace m4 {
 
 // Growable device buffer owned by a context.
+// ensure() over-allocates by 1/8 (plus 1 MiB) so that slowly growing inputs
+// do not reallocate every call; exact = true allocates exactly `bytes` and
+// also shrinks a larger buffer (the budgeted path must not hold more).
 struct DevBuf {
   char* ptr = nullptr;
   size_t cap = 0;
-  void ensure(size_t bytes, hipStream_t s);
+  void ensure(size_t bytes, hipStream_t s, bool exact = false);
   void release();
 };
 
@@ -24,6 +27,8 @@ Prep carve_prep(char* base, int64_t n, int64_t nnz);
 size_t stage_tmp_bytes(int64_t n, int64_t nnz, int64_t dmax, int num_cu);
 size_t c4_tmp_bytes(int64_t n);
 int set_error(m4_ctx* ctx, int code, const std::string& msg);
+// status and message of the error bits a call left in Scal::err
+int scal_error(m4_ctx* ctx, int err);
 int check_csr_args(const m4_csr* g);
 Tuning tuning_for(const m4_ctx* c, const m4_opts* o);
 void run_resident(m4_ctx* c, const int64_t* rp, const int32_t* col, int64_t n, int64_t nnz,
@@ -37,7 +42,7 @@ void destroy_ctx_extras(m4_ctx* c);
 // m4_batch.hip -- one persistent fused launch over a packed arena
 struct BatchArgs;
 struct BatchBuffers {
-  DevBuf dev, gscratch;
+  DevBuf dev;
   unsigned long long* h_out = nullptr;  // pinned [G][6]
   int* h_status = nullptr;              // pinned [G]
   char* h_stage = nullptr;              // pinned copy of a host arena
@@ -65,4 +70,8 @@ struct m4_ctx {
   std::string last_error;
   m4::BatchState* batch = nullptr;
   m4::PartState* part = nullptr;
+  // device bytes the context holds now (workspaces, batch buffers, Scal)
+  size_t held_bytes() const;
+  // frees every workspace except the budgeted path's (c->extra)
+  void release_resident();
 };

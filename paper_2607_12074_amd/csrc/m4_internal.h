@@ -41,6 +41,11 @@ constexpr int C4_MED_MAX = 65536;     // largest wedge bound of the medium bucke
 // vector loads aligned below a cursor may run past the end of the array.
 constexpr int NCOL_PAD = 256;
 
+// Error bits of Scal::err
+constexpr int ERR_INVALID = 1;  // malformed CSR (M4_VALIDATE)
+constexpr int ERR_RANGES = 2;   // ranged 4-cycle plan exceeded its bound
+constexpr int ERR_PROBE = 4;    // an open-addressing probe ran past its table size
+
 struct Scal {
   U128 acc[ACC_N + 1];
   unsigned long long stat[ST_N];

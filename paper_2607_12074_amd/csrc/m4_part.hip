@@ -153,9 +153,16 @@ int count_partitioned(m4_ctx* c, const m4_csr* g, const m4_opts* o, uint64_t out
   }
   if (rp[n] != nnz) return set_error(c, M4_ERANGE, "row_ptr[n] != nnz");
 
-  // the device side of the whole call lives in c->extra, sized to the budget
-  c->extra.ensure(budget, s);
-  Dev D{c->extra.ptr, budget};
+  // The device side of the whole call lives in c->extra.  Workspaces of
+  // earlier resident calls are freed first, and the region is allocated at
+  // exactly the budget less a reserve for the context's result block and the
+  // allocator's rounding, so the context never holds more than the budget.
+  c->release_resident();
+  constexpr uint64_t kReserve = 1 << 20;
+  if (budget <= 2 * kReserve) return set_error(c, M4_ENOMEM, "device budget below 2 MiB");
+  const uint64_t region = (budget - kReserve) & ~uint64_t(255);
+  c->extra.ensure(region, s, true);
+  Dev D{c->extra.ptr, region};
   auto up = [&](void* dst, const void* src, size_t bytes) {
     if (!bytes) return;
     const double t0 = now_ms();
@@ -486,7 +493,7 @@ int count_partitioned(m4_ctx* c, const m4_csr* g, const m4_opts* o, uint64_t out
   M4_HIP(hipMemcpyAsync(c->scal_host, c->scal, sizeof(Scal), hipMemcpyDeviceToHost, s));
   M4_HIP(hipStreamSynchronize(s));
   const Scal& h = *c->scal_host;
-  if (h.err) return set_error(c, M4_EINTERNAL, "4-cycle range plan exceeded its bound");
+  if (h.err) return scal_error(c, h.err);
   if (h.status == 3) return set_error(c, M4_EOVERFLOW, "a count is >= 2^64");
   if (h.status != 0) return set_error(c, M4_EINTERNAL, "closure consistency check failed");
   for (int i = 0; i < 6; i++) out[i] = h.out[i];
@@ -501,6 +508,7 @@ int count_partitioned(m4_ctx* c, const m4_csr* g, const m4_opts* o, uint64_t out
     st->halo_rows = halo_rows;
     st->ms_total = now_ms() - t_start;
     st->ms_h2d = t_h2d;
+    st->device_bytes = c->held_bytes();
   }
   return M4_OK;
 }

@@ -125,7 +125,7 @@ void launch_lane(m4_server* s, Lane& L) {
     memcpy(L.rowp.data() + L.voff[g] + g, r->rp.data(), (r->n + 1) * 8);
     if (r->nnz) memcpy(L.col.data() + L.eoff[g], r->col.data(), r->nnz * 4);
   }
-  batch_prepare(s->ctx, L.buf, L.plan, G, L.voff.data(), L.eoff.data(), L.rowp.data(), nullptr,
+  batch_prepare(s->ctx, L.buf, L.plan, G, L.voff.data(), L.eoff.data(), nullptr,
                 s->ctx->tune.batch_variant, s->ctx->tune.batch_light, 0, 0, L.stream);
   batch_stage(L.buf, L.plan, L.voff.data(), L.eoff.data(), L.rowp.data(), L.col.data());
   batch_enqueue(L.buf, L.plan, L.stream);

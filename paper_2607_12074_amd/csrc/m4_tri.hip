@@ -43,7 +43,7 @@ __global__ __launch_bounds__(NT, 5) void k_tri_lds(TriArgs A) {
   __shared__ int s_item;
   const int64_t b0 = A.start[A.bucket], cnt = A.start[A.bucket + 1] - b0;
   u128_t k4 = 0;
-  unsigned long long steps = 0, looks = 0, hits = 0, ksum = 0, wstream = 0, owners = 0,
+  unsigned long long steps = 0, looks = 0, hits = 0, ksum = 0, wread = 0, owners = 0,
                      escan = 0;
   for (;;) {
     if (threadIdx.x == 0) s_item = (int)atomicAdd(A.work, (unsigned)A.grab);
@@ -55,7 +55,7 @@ __global__ __launch_bounds__(NT, 5) void k_tri_lds(TriArgs A) {
     for (int64_t item = first; item < last; item++) {
       tri_owner<NT, false, false, HASH, true>(A, A.order[b0 + item], threadIdx.x, a, sst, soe,
                                               slen, spref, colcnt, tag, B, k4, steps, looks,
-                                              hits, ksum, wstream, escan, hk, hv);
+                                              hits, ksum, wread, escan, hk, hv);
       owners++;
     }
   }
@@ -67,7 +67,7 @@ __global__ __launch_bounds__(NT, 5) void k_tri_lds(TriArgs A) {
     block_add_u64<NT>(&A.scal->kstat[A.slot][0], escan);
     block_add_u64<NT>(&A.scal->kstat[A.slot][1], threadIdx.x == 0 ? owners : 0);
     block_add_u64<NT>(&A.scal->kstat[A.slot][2], ksum);
-    block_add_u64<NT>(&A.scal->kstat[A.slot][3], wstream);
+    block_add_u64<NT>(&A.scal->kstat[A.slot][3], wread);
   }
 }
 
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(NT) void k_tri_global(TriArgs A) {
   uint32_t* colcnt = (uint32_t*)(base + 5 * K + 1);
   uint32_t* tag = (uint32_t*)(base + 6 * K + 1);
   u128_t k4 = 0;
-  unsigned long long steps = 0, looks = 0, hits = 0, ksum = 0, wstream = 0, owners = 0,
+  unsigned long long steps = 0, looks = 0, hits = 0, ksum = 0, wread = 0, owners = 0,
                      escan = 0;
   for (;;) {
     if (threadIdx.x == 0) s_item = (int)atomicAdd(A.work, 1u);
@@ -95,7 +95,7 @@ __global__ __launch_bounds__(NT) void k_tri_global(TriArgs A) {
     if (item >= cnt) break;
     tri_owner<NT, true, false, false, true>(A, A.order[b0 + item], threadIdx.x, a, sst, soe, slen,
                                             spref, colcnt, tag, B, k4, steps, looks, hits, ksum,
-                                            wstream, escan);
+                                            wread, escan);
     owners++;
     __threadfence();
   }
@@ -107,7 +107,7 @@ __global__ __launch_bounds__(NT) void k_tri_global(TriArgs A) {
     block_add_u64<NT>(&A.scal->kstat[A.slot][0], escan);
     block_add_u64<NT>(&A.scal->kstat[A.slot][1], threadIdx.x == 0 ? owners : 0);
     block_add_u64<NT>(&A.scal->kstat[A.slot][2], ksum);
-    block_add_u64<NT>(&A.scal->kstat[A.slot][3], wstream);
+    block_add_u64<NT>(&A.scal->kstat[A.slot][3], wread);
   }
 }
 
@@ -162,7 +162,8 @@ __global__ __launch_bounds__(256) void k_hub_insert(const int32_t* __restrict__ 
                                                     const int32_t* __restrict__ hoff,
                                                     const int32_t* __restrict__ hubs,
                                                     const unsigned int* __restrict__ nhub,
-                                                    unsigned long long* __restrict__ htab) {
+                                                    unsigned long long* __restrict__ htab,
+                                                    int* __restrict__ err) {
   const int lane = threadIdx.x & (WAVE - 1);
   const int64_t nw = (int64_t)gridDim.x * (blockDim.x / WAVE);
   const int64_t nh = *nhub;
@@ -178,7 +179,15 @@ __global__ __launch_bounds__(256) void k_hub_insert(const int32_t* __restrict__ 
       const int32_t x = ncol[st + j];
       uint32_t h = hub_hash(x, bits);
       const unsigned long long e = ((unsigned long long)(uint32_t)x << 32) | (uint32_t)j;
-      while (atomicCAS(&htab[(int64_t)off + h], HUB_EMPTY, e) != HUB_EMPTY) h = (h + 1) & mask;
+      // L distinct keys in 2^bits >= 2L slots: a free slot within 2^bits probes
+      for (uint32_t probes = 0;
+           atomicCAS(&htab[(int64_t)off + h], HUB_EMPTY, e) != HUB_EMPTY; probes++) {
+        if (probes >= mask) {
+          atomicOr(err, ERR_PROBE);
+          break;
+        }
+        h = (h + 1) & mask;
+      }
     }
   }
 }
@@ -271,6 +280,7 @@ Launch tri_plan(const Prep& P, Scal* scal, const Tuning& tu, uint32_t flags, uin
   A.dplus = P.dplus;
   A.t = P.t;
   A.scal = scal;
+  A.err = &scal->err;
   A.flags = flags;
   A.cache_rows = cache_rows;
   std::array<int64_t, 17> hst;
@@ -283,7 +293,8 @@ Launch tri_plan(const Prep& P, Scal* scal, const Tuning& tu, uint32_t flags, uin
       k_hub_off<<<(unsigned)ceil_div(n, 256), 256, 0, ls>>>(hsz, hoff64, n, hoff);
       fill_u32(htab, 0xffffffffu, (size_t)hub_slots * 2, ls);
       k_hub_insert<<<(unsigned)(num_cu * 8), 256, 0, ls>>>(P.dplus, P.nptr, P.dlo, P.ncol, hoff,
-                                                            hub_list, &scal->nhub, htab);
+                                                            hub_list, &scal->nhub, htab,
+                                                            &scal->err);
       A.hoff = hoff;
       A.htab = htab;
       A.hub_min = tu.hub_min;

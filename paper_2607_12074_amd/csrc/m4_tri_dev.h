@@ -45,6 +45,9 @@ struct TriArgs {
   const unsigned long long* htab;
   int hub_min;            // 0: no tables
   int probe_w;            // row i is probed when probe_w (k-1-i) < 3 |N+(a[i])|
+  // bit ERR_PROBE is set here when a probe sequence runs past its table size
+  // (a broken table invariant); the probe then stops instead of spinning
+  int* err;
 };
 
 constexpr unsigned long long HUB_EMPTY = ~0ull;
@@ -98,8 +101,8 @@ __device__ __forceinline__ uint64_t k4_recompute(const int32_t* ncol, const int3
 // Work counters: steps (elements looked up or probed), looks/hits (frontier
 // cache), ksum (out-list entries of the owner), escan (sum of |N+(v)| over the
 // owner's out-neighbours v, the elements a scanning intersection reads),
-// wstream (sum over the triangles (u, v, w) of |N+(w)|, the list a
-// merge-based 4-clique step reads).
+// wread (4-byte words this routine reads from the out-lists and hub tables:
+// one per scanned element, two per 8-byte table slot probed).
 template <int NT, bool FRESH, bool WAVE_ONLY = false, bool HASH = false, bool PROBE = false>
 __device__ __forceinline__ void tri_owner(const TriArgs& A, int32_t u, const int tid, int32_t* a,
                                           int32_t* sst,
@@ -108,7 +111,7 @@ __device__ __forceinline__ void tri_owner(const TriArgs& A, int32_t u, const int
                                           u128_t& k4acc,
                                           unsigned long long& steps, unsigned long long& looks,
                                           unsigned long long& hits, unsigned long long& ksum,
-                                          unsigned long long& wstream,
+                                          unsigned long long& wread,
                                           unsigned long long& escan, int32_t* hk = nullptr,
                                           int16_t* hv = nullptr) {
   const int k = A.dplus[u];
@@ -141,11 +144,19 @@ __device__ __forceinline__ void tri_owner(const TriArgs& A, int32_t u, const int
   }
   TRI_SYNC();
   if (HASH) {
+    // k distinct keys in H >= 2k slots: a free slot is met within H probes
     for (int i = tid; i < k; i += NT) {
       const int32_t key = a[i];
       uint32_t h = ((uint32_t)key * 0x9E3779B1u) >> hshift;
-      while (atomicCAS(&hk[h], -1, key) != -1) h = (h + 1) & (uint32_t)(H - 1);
-      hv[h] = (int16_t)i;
+      int probes = 0;
+      while (atomicCAS(&hk[h], -1, key) != -1) {
+        h = (h + 1) & (uint32_t)(H - 1);
+        if (++probes >= H) {
+          atomicOr(A.err, ERR_PROBE);
+          break;
+        }
+      }
+      if (probes < H) hv[h] = (int16_t)i;
     }
   }
   // exclusive prefix of the row work of a[0..k) into spref[0..k]: |N+(a[i])|
@@ -228,31 +239,44 @@ __device__ __forceinline__ void tri_owner(const TriArgs& A, int32_t u, const int
         uint32_t h = ch[r];
         unsigned long long e = ce[r];
         pos = -1;
-        while (e != HUB_EMPTY) {
+        wread += 2;
+        // load <= 1/2: an empty slot ends every probe within mask + 1 steps
+        for (uint32_t probes = 0; e != HUB_EMPTY; probes++) {
           if ((int32_t)(e >> 32) == x) {
             pos = (int)(uint32_t)e;
             break;
           }
+          if (probes >= mask) {
+            atomicOr(A.err, ERR_PROBE);
+            break;
+          }
           h = (h + 1) & mask;
           e = A.htab[off + h];
+          wread += 2;
         }
         if (pos < 0) p = -1;
       } else if (HASH) {
         // x > a[ir], so a hit is always a position after ir
         pos = cj[r];
+        wread++;
         uint32_t h = ((uint32_t)x * 0x9E3779B1u) >> hshift;
         p = -1;
-        for (;;) {
+        for (int probes = 0;; probes++) {
           const int32_t key = hk[h];
           if (key == x) {
             p = hv[h];
             break;
           }
           if (key == -1) break;
+          if (probes >= H) {
+            atomicOr(A.err, ERR_PROBE);
+            break;
+          }
           h = (h + 1) & (uint32_t)(H - 1);
         }
       } else {
         pos = cj[r];
+        wread++;
         p = (int)lower_index(a, (int64_t)ir + 1, (int64_t)k, x);
         if (p >= k || a[p] != x) p = -1;
       }
@@ -289,7 +313,6 @@ __device__ __forceinline__ void tri_owner(const TriArgs& A, int32_t u, const int
         int p = (w << 6) + __ffsll((long long)bits) - 1;
         bits &= bits - 1;
         looks++;
-        wstream += (unsigned long long)slen[p];
         const bool cp = tag[p] == sig_key(2, (uint32_t)p, 3, 0);
         if (ci && cp) {
           hits++;

@@ -79,3 +79,32 @@ def test_missing_library_fails_loudly(monkeypatch):
         m4.lib()
     assert e.value.code == m4.M4_EDEVICE
     assert "missing" in str(e.value)
+
+
+def test_struct_sizes_match_a_c_compiler(tmp_path):
+    # every ABI struct as a C compiler lays it out from include/m4.h, against
+    # the binding's ctypes mirror (field offsets of the two largest structs too)
+    import subprocess
+    src = tmp_path / "sizes.c"
+    src.write_text(r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "m4.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(m4_csr), sizeof(m4_opts),
+         sizeof(m4_stats), sizeof(m4_batch), sizeof(m4_tuning), sizeof(m4_result),
+         offsetof(m4_stats, ms_kernel), offsetof(m4_stats, device_bytes),
+         offsetof(m4_result, t_submit_ms));
+  return 0;
+}
+''')
+    exe = tmp_path / "sizes"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    want = [ctypes.sizeof(m4.Csr), ctypes.sizeof(m4.Opts), ctypes.sizeof(m4.Stats),
+            ctypes.sizeof(m4.Batch), ctypes.sizeof(m4.Tuning), ctypes.sizeof(m4.Result),
+            m4.Stats.ms_kernel.offset, m4.Stats.device_bytes.offset,
+            m4.Result.t_submit_ms.offset]
+    assert got == want

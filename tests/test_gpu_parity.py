@@ -259,3 +259,28 @@ def test_repeat_is_deterministic(ctx):
     a = ctx.count(*g)
     b = ctx.count(*g)
     assert a == b == oracle.closure(*g)
+
+
+def test_overflow_boundary_of_the_star(ctx):
+    # C(n, 3) induced 3-stars: 4 801 000 leaves fit in 64 bits, 4 801 500 do
+    # not (the oracle reports status 3 for the same graph)
+    import paper_2607_12074_amd as m4
+    assert ctx.count(*G.star(4_801_000)) == (comb(4_801_000, 3), 0, 0, 0, 0, 0)
+    with pytest.raises(m4.M4Error) as e:
+        ctx.count(*G.star(4_801_500))
+    assert e.value.code == m4.M4_EOVERFLOW
+
+
+def test_web_scale24_matches_oracle_golden(ctx):
+    # the headline workload at its full size (268 M edges, CSR on the device
+    # as in the bench): counts and basis equal the oracle's stored values
+    import torch
+    gold = json.load(open(os.path.join(HERE, "golden", "rmat_web_s24.json")))
+    rp, col = gg.rmat_web(scale=24, edge_factor=16, seed=4)
+    assert (len(rp) - 1, len(col) // 2) == (gold["n"], gold["m"])
+    rp_d, col_d = torch.from_numpy(rp).cuda(), torch.from_numpy(col).cuda()
+    del rp, col
+    counts, st = ctx.count(rp_d, col_d, stats=True)
+    assert list(counts) == gold["counts"]
+    for k, v in gold["basis"].items():
+        assert st[k] == v, k

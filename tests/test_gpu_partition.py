@@ -109,3 +109,29 @@ def test_partition_with_ranged_medium_table(ctx):
             assert st[k] == rst[k], k
     finally:
         ctx.set_tuning(**saved)
+
+
+def test_budget_caps_the_device_footprint():
+    # A budgeted call frees the workspaces of earlier resident calls and
+    # holds no more than the budget: measured from the device's free memory
+    # (the library allocates with hipMalloc, outside torch's cache).
+    import torch
+    import paper_2607_12074_amd as m4
+    g = gg.rmat(15, 12, 0.57, 0.19, 0.19, 21)
+    ref = oracle.closure(*g)
+    c = m4.Context(0)
+    try:
+        free0, _ = torch.cuda.mem_get_info(0)
+        got, st = c.count(*g, stats=True)  # resident: grows the workspaces
+        assert got == ref
+        free1, _ = torch.cuda.mem_get_info(0)
+        assert free0 - free1 >= st["device_bytes"] // 2
+        budget = 24 << 20
+        got, st = c.count(*g, budget=budget, stats=True)
+        assert got == ref and st["partitions"] >= 3
+        assert st["device_bytes"] <= budget
+        free2, _ = torch.cuda.mem_get_info(0)
+        # allocation granularity aside, the context now holds <= the budget
+        assert free0 - free2 <= budget + (4 << 20), (free0 - free2, budget)
+    finally:
+        c.close()

@@ -292,6 +292,51 @@ def test_validate():
     assert not oracle.validate(rp, bad)
 
 
+def _edges_csr(n, pairs):
+    """CSR straight from directed (row, column) pairs, no symmetrisation or
+    cleaning, rows sorted: for malformed inputs the generators would repair."""
+    pairs = sorted(pairs)
+    rp = np.zeros(n + 1, dtype=np.int64)
+    for a, _ in pairs:
+        rp[a + 1] += 1
+    rp = np.cumsum(rp).astype(np.int64)
+    return rp, np.array([b for _, b in pairs], dtype=np.int32)
+
+
+def test_validate_rejects_each_malformation():
+    path = [(0, 1), (1, 0), (1, 2), (2, 1), (2, 3), (3, 2)]
+    assert oracle.validate(*_edges_csr(4, path))
+    # an edge listed in one row only (asymmetric)
+    assert not oracle.validate(*_edges_csr(4, path + [(0, 3)]))
+    # a self-loop, listed symmetrically
+    assert not oracle.validate(*_edges_csr(4, path + [(2, 2)]))
+    # a duplicate entry in a row (not strictly increasing)
+    assert not oracle.validate(*_edges_csr(4, path + [(0, 1), (1, 0)]))
+    # ids out of range: n and -1
+    rp, col = _edges_csr(4, path)
+    for bad_id in (4, -1, 1 << 30):
+        c2 = col.copy()
+        c2[-1] = bad_id
+        assert not oracle.validate(rp, c2), bad_id
+    # row offsets that go backwards, and a first offset that is not 0
+    rp2 = rp.copy()
+    rp2[2], rp2[3] = rp2[3], rp2[2]
+    assert not oracle.validate(rp2, col)
+    rp3 = rp.copy()
+    rp3[0] = 1
+    assert not oracle.validate(rp3, col)
+
+
+@pytest.mark.slow
+def test_overflow_boundary_of_the_star():
+    # K_{1,n} has C(n,3) induced 3-stars: 4 801 000 leaves stay below 2^64,
+    # 4 801 500 do not, and the oracle reports that as status 3
+    ok = G.star(4_801_000)
+    assert oracle.closure(*ok) == (comb(4_801_000, 3), 0, 0, 0, 0, 0)
+    with pytest.raises(oracle.OracleError, match="code 3"):
+        oracle.closure(*G.star(4_801_500))
+
+
 @pytest.mark.slow
 def test_er_workload_closure_equals_esu():
     g = gg.er_c1()
