@@ -68,6 +68,7 @@ KERNEL_SYMBOL = {
     "c4_window": "k_c4_window", "c4_med": "k_c4_hash<1024, 16384, 4>",
     "c4_hash": "k_c4_hash<256, 4096, 4>", "closure": "k_closure", "c4_plan": "k_c4_plan",
     "build": "(CSR builder kernels)", "tri_hubs": "k_hub_insert", "c4_desc": "k_c4_desc",
+    "c4_bin": "k_c4_bin",
 }
 
 
@@ -75,7 +76,7 @@ def alg_bytes(slot: int, st: dict, n: int, m: int) -> float:
     E, R, A = st["k_elems"][slot], st["k_rows"][slot], st["k_aux"][slot]
     if slot in TRI_SLOTS:
         return 4.0 * E + 4.0 * A + 8.0 * R
-    if slot in (8, 9, 10):
+    if slot in (8, 9, 10, 14):
         return 4.0 * E + 8.0 * A + 8.0 * R
     if slot == 11:
         return 12.0 * m + 4.0 * n

@@ -102,6 +102,7 @@ enum {
   M4_K_CLOSURE,       /* closure sums and exact inverse                         */
   M4_K_TRI_HUBS,      /* hub tables of the long out-lists (triangle probes)     */
   M4_K_C4_DESC,       /* 4-cycle window owners' segment descriptors             */
+  M4_K_C4_BIN,        /* 4-cycle owners binned by counter window                */
   M4_NK = 16
 };
 
@@ -115,9 +116,10 @@ enum {
  *                   per scanned element, two per 8-byte table slot probed)
  *   4-cycle slots:  k_elems = wedge endpoints counted, k_rows = owners,
  *                   k_aux = lower neighbours (segments), k_aux2 = segment
- *                   visits (window slot) or row entries read (table slots;
+ *                   visits (window slot), row entries read (table slots;
  *                   an owner counted in rank ranges reads its rows once per
- *                   pass)
+ *                   pass) or row entries read by the histogram and scatter
+ *                   passes (binned slot)
  *   closure:        k_elems = oriented edges, k_rows = vertices
  *   build:          k_elems = CSR entries, k_rows = vertices */
 typedef struct {
@@ -211,6 +213,12 @@ typedef struct {
                             ceil(bound / 12288), i.e. its endpoints are thin
                             over many windows (0 = never, default 64; needs
                             c4_med_max > 0)                                   */
+  int32_t c4_bin_win;    /* single graph: an owner above the one-pass medium
+                            bound whose endpoints span at least this many
+                            counter windows is counted by binning: its
+                            endpoints are sorted into per-window bins in
+                            device memory, then each bin is counted in LDS
+                            (0 = never, default 6)                            */
 } m4_tuning;
 
 int m4_get_tuning(const m4_ctx* ctx, m4_tuning* out);

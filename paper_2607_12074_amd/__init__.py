@@ -25,7 +25,8 @@ M4_PLAIN_LOOP = 0x20
 M4_SERIAL = 0x40
 M4_NK = 16
 KERNELS = ("build", "tri_global", "tri_1024", "tri_512", "tri_256", "tri_128", "tri_wave",
-           "c4_plan", "c4_window", "c4_med", "c4_hash", "closure", "tri_hubs", "c4_desc")
+           "c4_plan", "c4_window", "c4_med", "c4_hash", "closure", "tri_hubs", "c4_desc",
+           "c4_bin")
 NAMES = ("star", "path", "paw", "cycle", "diamond", "clique")
 BASIS = ("T", "K4", "C4_ni", "S", "P_ni", "Paw_ni", "D_ni", "sum_t")
 
@@ -80,7 +81,8 @@ class Tuning(ctypes.Structure):
     _fields_ = [("tri_wave_max", ctypes.c_int32), ("c4_light_max", ctypes.c_int32),
                 ("batch_variant", ctypes.c_int32), ("batch_light", ctypes.c_int32),
                 ("hub_min", ctypes.c_int32), ("c4_med_max", ctypes.c_int32),
-                ("probe_w", ctypes.c_int32), ("c4_med_win", ctypes.c_int32)]
+                ("probe_w", ctypes.c_int32), ("c4_med_win", ctypes.c_int32),
+                ("c4_bin_win", ctypes.c_int32)]
 
     def to_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}

@@ -110,7 +110,8 @@ size_t stage_tmp_bytes(int64_t n, int64_t nnz, int64_t dmax, int num_cu) {
 
 size_t c4_tmp_bytes(int64_t n) {
   return 2 * align256((size_t)(n + 1) * 8 + 8) + 4 * align256((size_t)n * 4 + 4) +
-         align256(radix_tmp_elems(n, 2) * 8) + align256(scan_tmp_elems(n) * 8) + 4096;
+         align256(radix_tmp_elems(n, C4_KEY_BITS) * 8) + align256(scan_tmp_elems(n) * 8) +
+         align256(32 * 8) + 4096;
 }
 
 int set_error(m4_ctx* ctx, int code, const std::string& msg) {

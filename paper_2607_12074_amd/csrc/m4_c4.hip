@@ -53,8 +53,11 @@ struct C4Args {
   unsigned int* work;
   Scal* scal;
   uint32_t flags;
-  const int64_t* seg_off;  // window owners: first descriptor of each owner
-  int4* desc;              // window owners: per-segment cursor descriptors
+  const int64_t* seg_off;  // window and binned owners: first descriptor of each owner
+  int4* desc;              // ... per-segment cursor descriptors
+  const int64_t* seg_pre;  // ... exclusive prefix of segment lengths within the owner
+  int32_t* bins;           // binned owners: per-block scratch of bin_cap endpoints
+  int64_t bin_cap;
   // counter zones of the window owners (ranks >= r1): 4-bit counters for
   // ranks [r1, z1) (degree <= 15), 8-bit for [z1, z2) (degree <= 255), 32-bit
   // from z2 on; aw and bw are the words of the first two zones
@@ -84,6 +87,8 @@ constexpr int C4_MED_BIN_MAX = 8192;
 constexpr int C4_MED_RANGES = 32;
 constexpr int64_t C4_MED_SPAN = (int64_t)C4_MED_SLOTS * C4_MED_BIN_MAX;
 constexpr int64_t C4_MED_CAP = 3 * C4_MED_SLOTS / 4;
+// most counter windows of a binned owner (its per-window histogram is in LDS)
+constexpr int C4_BIN_KMAX = 2048;
 
 // Windows of dense counters owner u needs over ranks [r1, u); zb holds the
 // first ranks of degree > 15 and > 255 (the zone bounds).
@@ -103,17 +108,23 @@ __device__ __forceinline__ int64_t c4_windows(const int64_t* zb, int64_t r1, int
 // lower neighbours, so an owner above the single-pass bound goes to the
 // ranged table only when its endpoints are thin over many windows:
 // 16 windows >= med_win ranges (med_win 0: never).
+// Beyond the one-pass table, an owner whose endpoints span at least bin_win
+// windows (and at most C4_BIN_KMAX) is binned: its endpoints are sorted into
+// per-window bins in device memory before counting, so a window costs only
+// its own endpoints instead of a pass over every lower neighbour's cursor.
 struct C4Plan {
-  int light_max, med_max, med_win;
+  int light_max, med_max, med_win, bin_win;
   const int64_t* zb;
   int64_t r1;
 };
 __device__ __forceinline__ uint32_t c4_bucket(const C4Plan& pl, int64_t w, int64_t u) {
   if (w <= pl.light_max) return CB_HASH;
+  if (pl.med_max > 0 && w <= pl.med_max && w <= C4_MED_CAP) return CB_MED;
+  const int64_t nwin = c4_windows(pl.zb, pl.r1, u);
+  if (pl.bin_win > 0 && nwin >= pl.bin_win && nwin <= C4_BIN_KMAX) return CB_BIN;
   if (pl.med_max <= 0) return CB_WIN;
-  if (w <= pl.med_max && w <= C4_MED_CAP) return CB_MED;
   if (pl.med_win > 0 && w <= C4_MED_MAX && u - pl.r1 < C4_MED_SPAN &&
-      16 * c4_windows(pl.zb, pl.r1, u) >= (int64_t)pl.med_win * ((w + C4_MED_CAP - 1) / C4_MED_CAP))
+      16 * nwin >= (int64_t)pl.med_win * ((w + C4_MED_CAP - 1) / C4_MED_CAP))
     return CB_MED;
   return CB_WIN;
 }
@@ -401,11 +412,12 @@ __global__ __launch_bounds__(NT) void k_c4_hash(C4Args A) {
 }
 
 // -------------------------------------------------------- window bucket
-// Segment descriptors of the window owners: for lower neighbour v of owner u
-// the cursor into row v (first entry >= r1), the end of the stored row and
-// the values at the cursor and 7 entries after it.  The windows stop at the first entry >= their
-// upper end, so the position of u in row v is never needed.  Built once per
-// owner by a block of its own.
+// Segment descriptors of the window and binned owners: for lower neighbour v
+// of owner u the cursor into row v (first entry >= r1), the position of u in
+// row v (the segment's end: entries from there on are not below u), and the
+// values at the cursor and 7 entries after it; seg_pre holds the exclusive
+// prefix of the segments' lengths within the owner.  Built once per owner by
+// a block of its own.
 __global__ __launch_bounds__(256) void k_c4_desc(const int32_t* __restrict__ order,
                                                  const int64_t* __restrict__ start,
                                                  const int64_t* __restrict__ seg_off,
@@ -414,19 +426,33 @@ __global__ __launch_bounds__(256) void k_c4_desc(const int32_t* __restrict__ ord
                                                  const int32_t* __restrict__ ncol,
                                                  const int32_t* __restrict__ lowcut,
                                                  const int32_t* __restrict__ row_len, int64_t r1,
-                                                 int4* __restrict__ desc) {
+                                                 int4* __restrict__ desc,
+                                                 int64_t* __restrict__ seg_pre) {
   const int64_t h = blockIdx.x;
   const int32_t u = order[start[CB_WIN] + h];
   const int64_t so = seg_off[h], base = nptr[u];
   const int nl = dlo[u];
-  for (int i = threadIdx.x; i < nl; i += 256) {
-    const int32_t v = ncol[base + i];
-    const int64_t rs = nptr[v];
-    const int64_t rend = row_len ? rs + row_len[v] : nptr[v + 1];
-    // first entry >= r1: precomputed for full rows, searched for stored prefixes
-    int64_t c = lowcut ? rs + lowcut[v] : lower_index(ncol, rs, rend, (int32_t)r1);
-    desc[so + i] = make_int4((int)c, (int)rend, c < rend ? ncol[c] : INT_MAX,
-                             c + 7 < rend ? ncol[c + 7] : INT_MAX);
+  int64_t run = 0;
+  for (int i0 = 0; i0 < nl; i0 += 256) {
+    const int i = i0 + (int)threadIdx.x;
+    int64_t len = 0;
+    if (i < nl) {
+      const int32_t v = ncol[base + i];
+      const int64_t rs = nptr[v];
+      const int64_t rend = row_len ? rs + row_len[v] : nptr[v + 1];
+      // u is an out-neighbour of v: search the out-part of row v
+      const int64_t e = lower_index(ncol, rs + dlo[v], rend, u);
+      // first entry >= r1: precomputed for full rows, searched for stored prefixes
+      int64_t c = lowcut ? rs + lowcut[v] : lower_index(ncol, rs, e, (int32_t)r1);
+      if (c > e) c = e;
+      desc[so + i] = make_int4((int)c, (int)e, c < e ? ncol[c] : INT_MAX,
+                               c + 7 < e ? ncol[c + 7] : INT_MAX);
+      len = e - c;
+    }
+    int64_t tot;
+    const int64_t ex = block_excl_scan64<256>(len, &tot);
+    if (i < nl) seg_pre[so + i] = run + ex;
+    run += tot;
   }
 }
 
@@ -443,7 +469,7 @@ __global__ void k_lowcut(const int64_t* __restrict__ nptr, const int32_t* __rest
 __global__ void k_c4_heavy_len(const int32_t* __restrict__ order, const int64_t* __restrict__ start,
                                const int32_t* __restrict__ dlo, int32_t* __restrict__ len) {
   const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t b = start[CB_WIN], H = start[CB_WIN + 1] - b;
+  const int64_t b = start[CB_WIN], H = start[CB_BIN + 1] - b;
   if (h < H) len[h] = dlo[order[b + h]];
 }
 
@@ -804,6 +830,238 @@ __global__ __launch_bounds__(W_NT) void k_c4_window(C4Args A) {
   }
 }
 
+// ----------------------------------------------------------- binned bucket
+// One owner per 1024-thread workgroup (heaviest first).  Its wedge endpoints
+// are the concatenation of its segments (rows of the lower neighbours from
+// the first rank >= r1 up to u); thread j walks the j-th 1/1024 of that
+// concatenation.  Every endpoint x falls in one counter window (the word of
+// its zoned counter, divided by the window's 32768 words).
+//   pass 1: histogram of the endpoints per window (LDS), one atomic per run
+//           of a window inside a chunk of a segment (rows are sorted);
+//   pass 2: the endpoints scattered into per-window bins of the block's
+//           device scratch (an LDS cursor per window, one atomic per run);
+//   pass 3: per window, its bin streamed (coalesced) through the dense LDS
+//           counters, each increment adding the counter's old value, then
+//           the touched counters cleared.
+// The scratch holds `cap` endpoints: windows are binned in consecutive
+// groups that fit it (a pass 2 per group); a single window with more
+// endpoints than `cap` is counted straight from the rows by a walk that
+// keeps only that window's endpoints.
+constexpr int BN_NT = 1024, BN_CH = 8;
+
+// window of a counter word and the window's zone kind / first rank
+__device__ __forceinline__ int32_t bin_of(const C4Args& A, int32_t x) {
+  return zone_word(A, x) / C4_WIN_WORDS;
+}
+
+template <class F>
+__device__ __forceinline__ void bin_walk(const C4Args& A, const int4* __restrict__ D,
+                                         const int64_t* __restrict__ pre, int nl, int64_t total,
+                                         F&& fn) {
+  // thread j: flattened endpoints [q0, q1), walked in chunks of at most
+  // BN_CH entries of one segment; fn(x[], take) sees each chunk
+  const int64_t per = (total + BN_NT - 1) / BN_NT;
+  int64_t q = (int64_t)threadIdx.x * per;
+  const int64_t q1 = q + per < total ? q + per : total;
+  if (q >= q1) return;
+  // segment holding q: last s with pre[s] <= q (segments may be empty)
+  int lo = 0, hi = nl;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] <= q) lo = mid + 1;
+    else hi = mid;
+  }
+  int sg = lo - 1;
+  int4 d = D[sg];
+  int64_t pos = d.x + (q - pre[sg]);
+  while (q < q1) {
+    while (pos >= d.y) {  // next non-empty segment
+      sg++;
+      d = D[sg];
+      pos = d.x;
+    }
+    int64_t take = d.y - pos;
+    if (take > q1 - q) take = q1 - q;
+    if (take > BN_CH) take = BN_CH;
+    int32_t x[BN_CH];
+#pragma unroll
+    for (int j = 0; j < BN_CH; j++) x[j] = j < take ? A.ncol[pos + j] : INT_MAX;
+    fn(x, (int)take);
+    pos += take;
+    q += take;
+  }
+}
+
+__global__ __launch_bounds__(BN_NT) void k_c4_bin(C4Args A) {
+  __shared__ uint32_t cnt[C4_WIN_WORDS];
+  __shared__ int32_t hist[C4_BIN_KMAX + 1];
+  __shared__ int32_t cur[C4_BIN_KMAX + 1];
+  __shared__ int s_item, s_g1;
+  const int tid = threadIdx.x;
+  const int64_t b0 = A.start[A.bucket], cnt_items = A.start[A.bucket + 1] - b0;
+  const int64_t hbase = b0 - A.start[CB_WIN];
+  int32_t* bins = A.bins + (int64_t)blockIdx.x * A.bin_cap;
+  u128_t acc = 0;
+  unsigned long long wedges = 0, owners = 0, segs = 0, reads = 0;
+  for (int i = tid; i < C4_WIN_WORDS; i += BN_NT) cnt[i] = 0;
+  for (;;) {
+    if (tid == 0) s_item = (int)atomicAdd(A.work, 1u);
+    __syncthreads();
+    const int64_t item = s_item;
+    __syncthreads();
+    if (item >= cnt_items) break;
+    const int64_t pos = cnt_items - 1 - item;  // heaviest owners (highest ranks) first
+    const int32_t u = A.order[b0 + pos];
+    const int64_t so = A.seg_off[hbase + pos];
+    const int nl = (int)(A.seg_off[hbase + pos + 1] - so);
+    const int4* D = A.desc + so;
+    const int64_t* pre = A.seg_pre + so;
+    const int64_t total = pre[nl - 1] + (D[nl - 1].y - D[nl - 1].x);
+    const int32_t uwords = zone_words(A, u);
+    const int K = (uwords + C4_WIN_WORDS - 1) / C4_WIN_WORDS;
+    if (tid == 0) {
+      owners++;
+      segs += (unsigned long long)nl;
+    }
+    // ---- pass 1: endpoints per window
+    for (int i = tid; i <= K; i += BN_NT) hist[i] = 0;
+    __syncthreads();
+    bin_walk(A, D, pre, nl, total, [&](const int32_t (&x)[BN_CH], int take) {
+      int w[BN_CH];
+#pragma unroll
+      for (int j = 0; j < BN_CH; j++) w[j] = j < take ? bin_of(A, x[j]) : -1;
+      // one add per run of a window (the chunk is sorted)
+#pragma unroll
+      for (int j = 0; j < BN_CH; j++) {
+        if (w[j] >= 0 && (j == 0 || w[j] != w[j - 1])) {
+          int len = 1;
+#pragma unroll
+          for (int k = j + 1; k < BN_CH; k++) len += w[k] == w[j];
+          atomicAdd(&hist[w[j]], len);
+        }
+      }
+    });
+    if (tid == 0) reads += (unsigned long long)total;
+    __syncthreads();
+    // ---- groups of windows whose endpoints fit the scratch
+    int g0 = 0;
+    while (g0 < K) {
+      if (tid == 0) {
+        int64_t sum = 0;
+        int g = g0;
+        while (g < K && sum + hist[g] <= A.bin_cap) sum += hist[g++];
+        s_g1 = g;
+      }
+      __syncthreads();
+      const int g1 = s_g1;
+      if (g1 == g0) {
+        // one window alone beyond the scratch: counted from the rows
+        const int32_t wlo = g0 * C4_WIN_WORDS;
+        bin_walk(A, D, pre, nl, total, [&](const int32_t (&x)[BN_CH], int take) {
+          uint64_t part = 0;
+#pragma unroll
+          for (int j = 0; j < BN_CH; j++) {
+            if (j < take && bin_of(A, x[j]) == g0) {
+              part += window_inc(A, cnt, wlo, x[j]);
+              wedges++;
+            }
+          }
+          acc += part;
+        });
+        if (tid == 0) reads += (unsigned long long)total;
+        __syncthreads();
+        const int used = uwords - wlo < C4_WIN_WORDS ? uwords - wlo : C4_WIN_WORDS;
+        for (int i = tid; i < used; i += BN_NT) cnt[i] = 0;
+        __syncthreads();
+        g0++;
+        continue;
+      }
+      // ---- pass 2: scatter the group's endpoints into per-window bins
+      if (tid == 0) {
+        int run = 0;
+        for (int g = g0; g < g1; g++) {
+          cur[g] = run;
+          run += hist[g];
+        }
+      }
+      __syncthreads();
+      bin_walk(A, D, pre, nl, total, [&](const int32_t (&x)[BN_CH], int take) {
+        int w[BN_CH];
+#pragma unroll
+        for (int j = 0; j < BN_CH; j++) {
+          w[j] = j < take ? bin_of(A, x[j]) : -1;
+          if (w[j] < g0 || w[j] >= g1) w[j] = -1;  // not in this group of windows
+        }
+        // a run of one window takes its slots with one add; the entries
+        // after the run's first follow it
+        int at = 0;
+#pragma unroll
+        for (int j = 0; j < BN_CH; j++) {
+          if (w[j] >= 0) {
+            if (j == 0 || w[j] != w[j - 1]) {
+              int len = 1;
+#pragma unroll
+              for (int k = j + 1; k < BN_CH; k++) len += w[k] == w[j];
+              at = atomicAdd(&cur[w[j]], len);
+            } else {
+              at++;
+            }
+            bins[at] = x[j];
+          }
+        }
+      });
+      if (tid == 0) reads += (unsigned long long)total;
+      __syncthreads();
+      // ---- pass 3: count every window of the group from its bin
+      int off = 0;
+      for (int g = g0; g < g1; g++) {
+        const int nb = hist[g];
+        if (nb == 0) continue;
+        const int32_t wlo = g * C4_WIN_WORDS;
+        const int32_t hnext =
+            wlo + C4_WIN_WORDS >= uwords ? u : zone_rank(A, wlo + C4_WIN_WORDS);
+        const int32_t hi = hnext < u ? hnext : u;
+        const int32_t wr = zone_rank(A, wlo);
+        const int kind =
+            hi <= A.z1 ? 0 : (wr >= A.z1 && hi <= A.z2 ? 1 : (wr >= A.z2 ? 2 : 3));
+        const int32_t* bg = bins + off;
+        auto count = [&](auto kind_tag) {
+          constexpr int KIND = decltype(kind_tag)::value;
+          uint64_t part = 0;
+          for (int q = tid; q < nb; q += BN_NT) part += window_inc_k<KIND>(A, cnt, wlo, wr, bg[q]);
+          acc += part;
+        };
+        switch (kind) {
+          case 0: count(std::integral_constant<int, 0>{}); break;
+          case 1: count(std::integral_constant<int, 1>{}); break;
+          case 2: count(std::integral_constant<int, 2>{}); break;
+          default: count(std::integral_constant<int, 3>{}); break;
+        }
+        if (tid == 0) wedges += (unsigned long long)nb;
+        __syncthreads();
+        // clear the counters: word by word for a sparse bin, else all used words
+        const int used = uwords - wlo < C4_WIN_WORDS ? uwords - wlo : C4_WIN_WORDS;
+        if (nb < used / 4) {
+          for (int q = tid; q < nb; q += BN_NT) cnt[zone_word(A, bg[q]) - wlo] = 0;
+        } else {
+          for (int i = tid; i < used; i += BN_NT) cnt[i] = 0;
+        }
+        __syncthreads();
+        off += nb;
+      }
+      g0 = g1;
+    }
+  }
+  block_add_u128<BN_NT>(&A.scal->acc[ACC_C4], acc);
+  if (A.flags & M4_STATS) {
+    block_add_u64<BN_NT>(&A.scal->stat[ST_WEDGES], wedges);
+    block_add_u64<BN_NT>(&A.scal->kstat[A.slot][0], wedges);
+    block_add_u64<BN_NT>(&A.scal->kstat[A.slot][1], owners);
+    block_add_u64<BN_NT>(&A.scal->kstat[A.slot][2], segs);
+    block_add_u64<BN_NT>(&A.scal->kstat[A.slot][3], reads);
+  }
+}
+
 inline unsigned blocks_for(int64_t n, int nt) { return (unsigned)ceil_div(n > 0 ? n : 1, nt); }
 
 }  // namespace
@@ -816,8 +1074,9 @@ Launch c4_plan(const Prep& P, const Classes& C, Scal* scal, const Tuning& tu, ui
   int64_t* wub = tmp.take<int64_t>(n);
   uint32_t* key = tmp.take<uint32_t>(n);
   int32_t* order = tmp.take<int32_t>(n);
-  int64_t* rtmp = tmp.take<int64_t>(radix_tmp_elems(n, 2));
-  int64_t* start = tmp.take<int64_t>(CB_N + 3);
+  int64_t* rtmp = tmp.take<int64_t>(radix_tmp_elems(n, C4_KEY_BITS));
+  // bucket starts (C4_START_SLOTS), then the two zone bounds
+  int64_t* start = tmp.take<int64_t>(C4_START_SLOTS + 2);
   int32_t* hlen = tmp.take<int32_t>(n);
   int64_t* seg_off = tmp.take<int64_t>(n + 1);
   int64_t* stmp = tmp.take<int64_t>(scan_tmp_elems(n));
@@ -826,8 +1085,9 @@ Launch c4_plan(const Prep& P, const Classes& C, Scal* scal, const Tuning& tu, ui
     throw Fail(M4_EINTERNAL, "workspace too small (c4)");
   fill_u32(&scal->work_c4[0], 0, 8, s);
   // zone bounds first: the planner needs every owner's window count
-  k_zone_bounds<<<1, 64, 0, s>>>(P.dr, n, start + CB_N + 1);
-  C4Plan pl{tu.c4_light_max, tu.c4_med_max, tu.c4_med_win, start + CB_N + 1, C.r1};
+  int64_t* zbounds = start + C4_START_SLOTS;
+  k_zone_bounds<<<1, 64, 0, s>>>(P.dr, n, zbounds);
+  C4Plan pl{tu.c4_light_max, tu.c4_med_max, tu.c4_med_win, tu.c4_bin_win, zbounds, C.r1};
   // rows by degree: <= 64 with 8 lanes, <= 4096 with a wavefront, longer
   // rows with a workgroup
   const int64_t b64 = C.bound[4], b4096 = C.bound[7];
@@ -841,25 +1101,45 @@ Launch c4_plan(const Prep& P, const Classes& C, Scal* scal, const Tuning& tu, ui
   if (n > b4096)
     k_c4_plan_big<<<(unsigned)(n - b4096), 1024, 0, s>>>(P.nptr, P.ncol, P.dr, P.dlo, b4096, C.r1,
                                                          pl, wub, key, P.own_lo, P.hi());
-  radix_pass(key, nullptr, n, 0, 2, nullptr, order, rtmp, start, s);
-  std::array<int64_t, CB_N + 3> hstart;
+  radix_pass(key, nullptr, n, 0, C4_KEY_BITS, nullptr, order, rtmp, start, s);
+  std::array<int64_t, C4_START_SLOTS + 2> hstart;
   M4_HIP(hipMemcpyAsync(hstart.data(), start, sizeof(int64_t) * hstart.size(),
                         hipMemcpyDeviceToHost, s));
   M4_HIP(hipStreamSynchronize(s));
-  // counter zones of the window owners
-  const int64_t z1 = std::max<int64_t>(hstart[CB_N + 1], C.r1);
-  const int64_t z2 = std::max<int64_t>(hstart[CB_N + 2], z1);
+  // counter zones of the window and binned owners
+  const int64_t z1 = std::max<int64_t>(hstart[C4_START_SLOTS], C.r1);
+  const int64_t z2 = std::max<int64_t>(hstart[C4_START_SLOTS + 1], z1);
   const int64_t aw = (z1 - C.r1 + 7) >> 3, bw = (z2 - z1 + 3) >> 2;
-  const int64_t H = hstart[CB_WIN + 1] - hstart[CB_WIN];
+  // window and binned owners are adjacent in the bucket order: one set of
+  // segment descriptors serves both
+  const int64_t H = hstart[CB_BIN + 1] - hstart[CB_WIN];
+  const int64_t HB = hstart[CB_BIN + 1] - hstart[CB_BIN];
   int4* desc = nullptr;
+  int64_t* seg_pre = nullptr;
+  int32_t* bins = nullptr;
+  int64_t bin_cap = 0;
+  unsigned bin_grid = 0;
   if (H > 0) {
     k_c4_heavy_len<<<blocks_for(H, 256), 256, 0, s>>>(order, start, P.dlo, hlen);
     scan_i32(hlen, H, seg_off, stmp, s);
     int64_t nseg = 0;
     M4_HIP(hipMemcpyAsync(&nseg, seg_off + H, 8, hipMemcpyDeviceToHost, s));
     M4_HIP(hipStreamSynchronize(s));
-    desc = reinterpret_cast<int4*>(big_scratch((size_t)(nseg > 0 ? nseg : 1) * sizeof(int4)));
-    if (!desc) throw Fail(M4_ENOMEM, "no room for 4-cycle segment descriptors");
+    const size_t db = ((size_t)(nseg > 0 ? nseg : 1) * sizeof(int4) + 255) & ~size_t(255);
+    const size_t pb = ((size_t)(nseg > 0 ? nseg : 1) * 8 + 255) & ~size_t(255);
+    // binned owners: per block scratch of at most 2^21 endpoints (no owner
+    // has more endpoints than the graph has CSR entries)
+    size_t bb = 0;
+    if (HB > 0) {
+      bin_cap = std::min<int64_t>(int64_t(1) << 21, std::max<int64_t>(P.nnz, 1));
+      bin_grid = (unsigned)std::min<int64_t>(num_cu, HB);
+      bb = (size_t)bin_grid * (size_t)bin_cap * 4;
+    }
+    char* scr = big_scratch(db + pb + bb);
+    if (!scr) throw Fail(M4_ENOMEM, "no room for 4-cycle segment descriptors");
+    desc = reinterpret_cast<int4*>(scr);
+    seg_pre = reinterpret_cast<int64_t*>(scr + db);
+    if (HB > 0) bins = reinterpret_cast<int32_t*>(scr + db + pb);
   }
   if (kt) kt->end(M4_K_C4_PLAN, s);
 
@@ -877,6 +1157,9 @@ Launch c4_plan(const Prep& P, const Classes& C, Scal* scal, const Tuning& tu, ui
   A.flags = flags;
   A.seg_off = seg_off;
   A.desc = desc;
+  A.seg_pre = seg_pre;
+  A.bins = bins;
+  A.bin_cap = bin_cap;
   A.z1 = (int32_t)z1;
   A.z2 = (int32_t)z2;
   A.aw = (int32_t)aw;
@@ -891,10 +1174,18 @@ Launch c4_plan(const Prep& P, const Classes& C, Scal* scal, const Tuning& tu, ui
         k_lowcut<<<blocks_for(n, 256), 256, 0, ls>>>(P.nptr, P.ncol, P.row_len, n, C.r1, lowcut);
       k_c4_desc<<<(unsigned)H, 256, 0, ls>>>(order, start, seg_off, P.nptr, P.dlo, P.ncol,
                                              P.row_len ? nullptr : lowcut, P.row_len, C.r1,
-                                             desc);
+                                             desc, seg_pre);
       if (kt) kt->end(M4_K_C4_DESC, ls);
     }
     // heavy owners first: one 1024-thread workgroup per CU
+    if (HB > 0) {
+      A.bucket = CB_BIN;
+      A.slot = M4_K_C4_BIN;
+      A.work = &scal->work_c4[CB_BIN];
+      if (kt) kt->begin(M4_K_C4_BIN, ls);
+      k_c4_bin<<<bin_grid, BN_NT, 0, ls>>>(A);
+      if (kt) kt->end(M4_K_C4_BIN, ls);
+    }
     if (hstart[CB_WIN + 1] > hstart[CB_WIN]) {
       A.bucket = CB_WIN;
       A.slot = M4_K_C4_WINDOW;

@@ -28,7 +28,10 @@ enum Stat { ST_STEPS = 0, ST_WEDGES, ST_LOOKUPS, ST_HITS, ST_N = 8 };
 // Triangle-owner buckets by out-degree k = d+(u).
 enum TriBucket { TB_NONE = 0, TB_WAVE, TB_LDS, TB_GLOBAL, TB_N = 4 };
 // 4-cycle-owner buckets by wedge bound.
-enum C4Bucket { CB_NONE = 0, CB_HASH, CB_MED, CB_WIN, CB_N = 4 };
+enum C4Bucket { CB_NONE = 0, CB_HASH, CB_MED, CB_WIN, CB_BIN, CB_N = 5 };
+// radix digits of the 4-cycle bucket keys and slots of their bucket starts
+constexpr int C4_KEY_BITS = 4;
+constexpr int C4_START_SLOTS = (1 << C4_KEY_BITS) + 1;
 
 // Largest out-degree handled with the bitmap rows in LDS.
 constexpr int TRI_LDS_MAX = 1024;
@@ -114,6 +117,8 @@ struct Tuning {
   int hub_min = 32;         // out-degree from which a vertex gets a hub table (0: none)
   int probe_w = 4;          // weight of a hub-table probe against a scanned element (x 1/3)
   int c4_med_win = 64;      // ranged medium owners: 16 windows >= this per range (0: none)
+  int c4_bin_win = 6;       // owners above the one-pass medium bound whose endpoints span at
+                            // least this many counter windows are binned by window (0: never)
 };
 
 // Optional per-launch HIP event pairs (M4_TIMING).

@@ -122,7 +122,9 @@ int count_partitioned(m4_ctx* c, const m4_csr* g, const m4_opts* o, uint64_t out
                       m4_stats* st) {
   hipStream_t s = (o && o->hip_stream) ? (hipStream_t)o->hip_stream : c->stream;
   const uint32_t flags = o ? o->flags : 0;
-  const Tuning tu = tuning_for(c, o);
+  Tuning tu = tuning_for(c, o);
+  // the binned 4-cycle owners need scratch a partition's budget cannot spare
+  tu.c4_bin_win = 0;
   const int64_t n = g->n, nnz = g->nnz, m = nnz / 2;
   uint64_t budget = o ? o->device_budget_bytes : 0;
   if (budget == 0) budget = resident_bytes(n, nnz, c->num_cu) / 3 + (1 << 20);
@@ -158,8 +160,8 @@ int count_partitioned(m4_ctx* c, const m4_csr* g, const m4_opts* o, uint64_t out
   // exactly the budget less a reserve for the context's result block and the
   // allocator's rounding, so the context never holds more than the budget.
   c->release_resident();
-  constexpr uint64_t kReserve = 1 << 20;
-  if (budget <= 2 * kReserve) return set_error(c, M4_ENOMEM, "device budget below 2 MiB");
+  constexpr uint64_t kReserve = 16 << 10;  // the result block and rounding
+  if (budget <= 4 * kReserve) return set_error(c, M4_ENOMEM, "device budget below 64 KiB");
   const uint64_t region = (budget - kReserve) & ~uint64_t(255);
   c->extra.ensure(region, s, true);
   Dev D{c->extra.ptr, region};
@@ -304,8 +306,7 @@ int count_partitioned(m4_ctx* c, const m4_csr* g, const m4_opts* o, uint64_t out
   fill_u32(P.t, 0, (size_t)m, s);
   const size_t fixed_used = D.used;
   const size_t tri_tmp = 2 * al(n * 4 + 4) + al(radix_tmp_elems(n, 4) * 8) + 4096;
-  const size_t c4_tmp = 2 * al((n + 1) * 8 + 8) + 4 * al(n * 4 + 4) +
-                        al(radix_tmp_elems(n, 2) * 8) + al(scan_tmp_elems(n) * 8) + 4096;
+  const size_t c4_tmp = c4_tmp_bytes(n);
   // scratch that a kernel stage sizes at run time comes from the tail of the
   // budget region, after the stage's work arrays
   size_t scratch_floor = 0;
@@ -439,7 +440,7 @@ int count_partitioned(m4_ctx* c, const m4_csr* g, const m4_opts* o, uint64_t out
           fresh.push_back({v, (int32_t)len});
         }
         for (auto& f : fresh) add += (size_t)f.second * 4 + 32;
-        add += (size_t)H.dlo[u] * 16;  // segment descriptors
+        add += (size_t)H.dlo[u] * 24 + 512;  // segment descriptors and their prefix
         if (bytes + add > cap_rows && hi > lo) break;
         bytes += add;
         for (int64_t p = ub; p < ue; p++)

