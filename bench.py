@@ -445,6 +445,9 @@ def run_budget_leg(ctx, rp, col, budget_gb, resident_counts):
             "halo_amplification": st["halo_rows"] / n,
             "h2d_over_csr": st["h2d_bytes"] / (8.0 * (n + 1) + 8.0 * m),
             "device_bytes": st["device_bytes"],
+            "ms_phases": {"order_and_rows": st["ms_build"], "triangles": st["ms_tri"],
+                          "four_cycles": st["ms_c4"], "closure": st["ms_closure"],
+                          "host_planning_and_gathers": st["ms_host"]},
             "equal_to_resident": tuple(counts) == tuple(resident_counts),
             "note": "host CSR in, counts out; the partition plan, halo gathers and "
                     "uploads are inside the time"}
@@ -595,7 +598,8 @@ def main():
     if args.budget_gb > 0:
         budget = run_budget_leg(ctx, rp, col, args.budget_gb, counts)
         note(f"budget leg ({args.budget_gb} GB): {budget['ms'] / 1e3:.2f} s, "
-             f"{budget['partitions']} partitions, equal {budget['equal_to_resident']}")
+             f"{budget['partitions']} partitions, equal {budget['equal_to_resident']}, "
+             "phases ms " + ", ".join(f"{k} {v:.0f}" for k, v in budget["ms_phases"].items()))
 
     digest = source_digest()
     dname = main_leg["dname"]

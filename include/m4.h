@@ -145,6 +145,10 @@ typedef struct {
    * budget it never exceeds device_budget_bytes: the call first frees the
    * workspaces of earlier unbudgeted calls and allocates exactly the budget. */
   uint64_t device_bytes;
+  /* partitioned calls: host time spent planning the owner ranges and
+   * gathering their halo rows into pinned memory (ms_build, ms_tri, ms_c4 and
+   * ms_closure then hold the wall time of each phase)                        */
+  double ms_host;
 } m4_stats;
 
 typedef struct m4_ctx m4_ctx;
@@ -219,6 +223,10 @@ typedef struct {
                             endpoints are sorted into per-window bins in
                             device memory, then each bin is counted in LDS
                             (0 = never, default 6)                            */
+  int32_t c4_bin_cap;    /* single graph: endpoints one binning workgroup's
+                            device scratch holds (0 = 2^20, else 64..2^24);
+                            an owner with more is binned in several rank
+                            ranges                                           */
 } m4_tuning;
 
 int m4_get_tuning(const m4_ctx* ctx, m4_tuning* out);

@@ -61,7 +61,7 @@ class Stats(ctypes.Structure):
                 ("ms_total", ctypes.c_double), ("ms_build", ctypes.c_double),
                 ("ms_tri", ctypes.c_double), ("ms_c4", ctypes.c_double),
                 ("ms_closure", ctypes.c_double), ("ms_h2d", ctypes.c_double),
-                ("device_bytes", ctypes.c_uint64)]
+                ("device_bytes", ctypes.c_uint64), ("ms_host", ctypes.c_double)]
 
     def to_dict(self):
         d = {k: int(v) for k, v in zip(BASIS, self.basis)}
@@ -82,7 +82,7 @@ class Tuning(ctypes.Structure):
                 ("batch_variant", ctypes.c_int32), ("batch_light", ctypes.c_int32),
                 ("hub_min", ctypes.c_int32), ("c4_med_max", ctypes.c_int32),
                 ("probe_w", ctypes.c_int32), ("c4_med_win", ctypes.c_int32),
-                ("c4_bin_win", ctypes.c_int32)]
+                ("c4_bin_win", ctypes.c_int32), ("c4_bin_cap", ctypes.c_int32)]
 
     def to_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}

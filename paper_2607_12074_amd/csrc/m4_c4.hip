@@ -56,6 +56,7 @@ struct C4Args {
   const int64_t* seg_off;  // window and binned owners: first descriptor of each owner
   int4* desc;              // ... per-segment cursor descriptors
   const int64_t* seg_pre;  // ... exclusive prefix of segment lengths within the owner
+  const int32_t* seg_cnt;  // ... non-empty segments of each owner
   int32_t* bins;           // binned owners: per-block scratch of bin_cap endpoints
   int64_t bin_cap;
   // counter zones of the window owners (ranks >= r1): 4-bit counters for
@@ -87,8 +88,9 @@ constexpr int C4_MED_BIN_MAX = 8192;
 constexpr int C4_MED_RANGES = 32;
 constexpr int64_t C4_MED_SPAN = (int64_t)C4_MED_SLOTS * C4_MED_BIN_MAX;
 constexpr int64_t C4_MED_CAP = 3 * C4_MED_SLOTS / 4;
-// most counter windows of a binned owner (its per-window histogram is in LDS)
-constexpr int C4_BIN_KMAX = 2048;
+// most counter windows of a binned owner (its per-bucket histogram, over
+// buckets 16 times finer, is in LDS)
+constexpr int C4_BIN_KMAX = 248;
 
 // Windows of dense counters owner u needs over ranks [r1, u); zb holds the
 // first ranks of degree > 15 and > 255 (the zone bounds).
@@ -415,9 +417,10 @@ __global__ __launch_bounds__(NT) void k_c4_hash(C4Args A) {
 // Segment descriptors of the window and binned owners: for lower neighbour v
 // of owner u the cursor into row v (first entry >= r1), the position of u in
 // row v (the segment's end: entries from there on are not below u), and the
-// values at the cursor and 7 entries after it; seg_pre holds the exclusive
-// prefix of the segments' lengths within the owner.  Built once per owner by
-// a block of its own.
+// values at the cursor and 7 entries after it.  Only non-empty segments are
+// kept (a lower neighbour of degree 1, say, has none), packed from the
+// owner's first slot; seg_cnt[h] is their number and seg_pre (binned owners
+// only) the exclusive prefix of their lengths.  One block per owner.
 __global__ __launch_bounds__(256) void k_c4_desc(const int32_t* __restrict__ order,
                                                  const int64_t* __restrict__ start,
                                                  const int64_t* __restrict__ seg_off,
@@ -427,33 +430,39 @@ __global__ __launch_bounds__(256) void k_c4_desc(const int32_t* __restrict__ ord
                                                  const int32_t* __restrict__ lowcut,
                                                  const int32_t* __restrict__ row_len, int64_t r1,
                                                  int4* __restrict__ desc,
-                                                 int64_t* __restrict__ seg_pre) {
+                                                 int64_t* __restrict__ seg_pre,
+                                                 int32_t* __restrict__ seg_cnt) {
   const int64_t h = blockIdx.x;
   const int32_t u = order[start[CB_WIN] + h];
   const int64_t so = seg_off[h], base = nptr[u];
   const int nl = dlo[u];
-  int64_t run = 0;
+  int64_t run = 0, kept = 0;
   for (int i0 = 0; i0 < nl; i0 += 256) {
     const int i = i0 + (int)threadIdx.x;
-    int64_t len = 0;
+    int64_t len = 0, c = 0, e = 0;
     if (i < nl) {
       const int32_t v = ncol[base + i];
       const int64_t rs = nptr[v];
       const int64_t rend = row_len ? rs + row_len[v] : nptr[v + 1];
       // u is an out-neighbour of v: search the out-part of row v
-      const int64_t e = lower_index(ncol, rs + dlo[v], rend, u);
+      e = lower_index(ncol, rs + dlo[v], rend, u);
       // first entry >= r1: precomputed for full rows, searched for stored prefixes
-      int64_t c = lowcut ? rs + lowcut[v] : lower_index(ncol, rs, e, (int32_t)r1);
+      c = lowcut ? rs + lowcut[v] : lower_index(ncol, rs, e, (int32_t)r1);
       if (c > e) c = e;
-      desc[so + i] = make_int4((int)c, (int)e, c < e ? ncol[c] : INT_MAX,
-                               c + 7 < e ? ncol[c + 7] : INT_MAX);
       len = e - c;
     }
-    int64_t tot;
+    int64_t tot, ktot;
     const int64_t ex = block_excl_scan64<256>(len, &tot);
-    if (i < nl) seg_pre[so + i] = run + ex;
+    const int64_t kx = block_excl_scan64<256>(len > 0 ? 1 : 0, &ktot);
+    if (len > 0) {
+      const int64_t at = so + kept + kx;
+      desc[at] = make_int4((int)c, (int)e, ncol[c], c + 7 < e ? ncol[c + 7] : INT_MAX);
+      if (seg_pre) seg_pre[at] = run + ex;
+    }
     run += tot;
+    kept += ktot;
   }
+  if (threadIdx.x == 0) seg_cnt[h] = (int32_t)kept;
 }
 
 // entries below r1 (degree <= 1) at the head of every sorted row
@@ -650,7 +659,7 @@ __global__ __launch_bounds__(W_NT) void k_c4_window(C4Args A) {
     const int64_t pos = cnt_items - 1 - item;
     const int32_t u = A.order[b0 + pos];
     const int64_t so = A.seg_off[hbase + pos];
-    const int nl = (int)(A.seg_off[hbase + pos + 1] - so);
+    const int nl = A.seg_cnt[hbase + pos];
     int4* D = A.desc + so;
     // owners with at most W_BATCH segments keep each thread's descriptors in
     // registers from window to window
@@ -831,225 +840,452 @@ __global__ __launch_bounds__(W_NT) void k_c4_window(C4Args A) {
 }
 
 // ----------------------------------------------------------- binned bucket
-// One owner per 1024-thread workgroup (heaviest first).  Its wedge endpoints
-// are the concatenation of its segments (rows of the lower neighbours from
-// the first rank >= r1 up to u); thread j walks the j-th 1/1024 of that
-// concatenation.  Every endpoint x falls in one counter window (the word of
-// its zoned counter, divided by the window's 32768 words).
-//   pass 1: histogram of the endpoints per window (LDS), one atomic per run
-//           of a window inside a chunk of a segment (rows are sorted);
-//   pass 2: the endpoints scattered into per-window bins of the block's
-//           device scratch (an LDS cursor per window, one atomic per run);
-//   pass 3: per window, its bin streamed (coalesced) through the dense LDS
-//           counters, each increment adding the counter's old value, then
-//           the touched counters cleared.
-// The scratch holds `cap` endpoints: windows are binned in consecutive
-// groups that fit it (a pass 2 per group); a single window with more
-// endpoints than `cap` is counted straight from the rows by a walk that
-// keeps only that window's endpoints.
-constexpr int BN_NT = 1024, BN_CH = 8;
+// One owner at a time per 512-thread workgroup (two per CU), heaviest first.
+// Its wedge endpoints are the concatenation of its non-empty segments (rows
+// of the lower neighbours from the first rank >= r1 up to u).  The counter
+// words of the ranks [r1, u) are cut into fine buckets of BF_WORDS words.
+//   pass 1: each wave walks a contiguous share of the concatenation, 64
+//           endpoints a step and BF_UNROLL steps in flight, and counts the
+//           endpoints per bucket in LDS (one atomic per run of lanes with
+//           the same segment and bucket); a block prefix turns the counts
+//           into bucket starts;
+//   pass 2: the same walk scatters the endpoints into their buckets in the
+//           block's device scratch (one cursor atomic per run);
+//   pass 3: waves take groups of consecutive buckets, a group being the
+//           buckets that start within one stretch of BF_GROUP positions of
+//           the scatter, and count each in a private 8 KiB LDS region: the
+//           group's small buckets in an open-addressing table of (rank,
+//           count) pairs, a bucket above BF_GROUP endpoints alone in dense
+//           zoned counters (it spans BF_WORDS words); every increment adds
+//           the counter's old value.  Dense buckets above BF_BIG endpoints
+//           are counted afterwards by the whole block.
+// No barrier is taken per bucket.  The scratch holds `cap` endpoints: an
+// owner with more is scattered in consecutive bucket ranges that fit, one
+// pass 2 and 3 per range; a single bucket above `cap` is counted straight
+// from the rows by a walk that keeps only its endpoints.
+constexpr int BN_NT = 512, BN_NW = BN_NT / WAVE;
+constexpr int BF_SHIFT = 11, BF_WORDS = 1 << BF_SHIFT;  // 8 KiB of counters per wave
+constexpr int BF_KMAX = 3968;    // fine buckets per owner (two workgroups' LDS per CU)
+constexpr int BF_GROUP = 192;    // scatter positions per group
+constexpr int BF_HBITS = BF_SHIFT - 1, BF_HSLOTS = 1 << BF_HBITS;  // 64-bit slots
+constexpr int BF_BIG = 4096;     // dense buckets above this: the whole block
+constexpr int BF_BIGLIST = 48;
+constexpr int BF_UNROLL = 8;     // walk steps in flight per wave
+static_assert((int64_t)C4_BIN_KMAX * C4_WIN_WORDS <= (int64_t)BF_KMAX * BF_WORDS,
+              "a binned owner's fine buckets must fit the LDS histogram");
+static_assert(2 * BF_GROUP <= BF_HSLOTS / 2, "a hash group must keep its table half empty");
 
-// window of a counter word and the window's zone kind / first rank
-__device__ __forceinline__ int32_t bin_of(const C4Args& A, int32_t x) {
-  return zone_word(A, x) / C4_WIN_WORDS;
+__device__ __forceinline__ int32_t fbin_of(const C4Args& A, int32_t x) {
+  return zone_word(A, x) >> BF_SHIFT;
 }
 
+__device__ __forceinline__ int64_t readlane64(int64_t v, int l) {
+  const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), l);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Per-wave view of 64 consecutive segments from sbase: lane j holds the
+// concatenated start of segment sbase + 1 + j (far beyond the end past the
+// last segment) and, for segment sbase + j, its row index minus its
+// concatenated start (so an endpoint at position q of that segment sits at
+// ncol[q + delta]; both are below 2^31).
+struct SegView {
+  int sbase;
+  int64_t B;
+  int32_t delta;
+};
+constexpr int64_t SEG_FAR = int64_t(1) << 62;
+constexpr int WALK_PER = 4;                     // positions per lane and step
+constexpr int WALK_STEP = WAVE * WALK_PER;      // positions per wave and step
+constexpr int WALK_UNROLL = 2;                  // steps in flight
+
+__device__ __forceinline__ void seg_view_load(const int4* __restrict__ D,
+                                              const int64_t* __restrict__ pre, int nl, int sbase,
+                                              SegView& v) {
+  const int j = sbase + (int)(threadIdx.x & (WAVE - 1));
+  v.sbase = sbase;
+  v.B = j + 1 < nl ? pre[j + 1] : SEG_FAR;
+  v.delta = j < nl ? (int32_t)((int64_t)D[j].x - pre[j]) : 0;
+}
+
+// Walks the endpoints [q_lo, q_hi) of one owner on one wave (s_lo: the
+// segment holding q_lo); emit(x, valid) sees every position once.  A step
+// gives each lane WALK_PER consecutive positions; the segment of each is the
+// view's boundaries at or below it, counted over the few boundaries inside
+// the step.  Where 64 segments end within a step (very short segments) the
+// step falls back to one position per lane.
 template <class F>
-__device__ __forceinline__ void bin_walk(const C4Args& A, const int4* __restrict__ D,
-                                         const int64_t* __restrict__ pre, int nl, int64_t total,
-                                         F&& fn) {
-  // thread j: flattened endpoints [q0, q1), walked in chunks of at most
-  // BN_CH entries of one segment; fn(x[], take) sees each chunk
-  const int64_t per = (total + BN_NT - 1) / BN_NT;
-  int64_t q = (int64_t)threadIdx.x * per;
-  const int64_t q1 = q + per < total ? q + per : total;
-  if (q >= q1) return;
-  // segment holding q: last s with pre[s] <= q (segments may be empty)
-  int lo = 0, hi = nl;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (pre[mid] <= q) lo = mid + 1;
-    else hi = mid;
-  }
-  int sg = lo - 1;
-  int4 d = D[sg];
-  int64_t pos = d.x + (q - pre[sg]);
-  while (q < q1) {
-    while (pos >= d.y) {  // next non-empty segment
-      sg++;
-      d = D[sg];
-      pos = d.x;
+__device__ __forceinline__ void bin_walk(const int32_t* __restrict__ ncol,
+                                         const int4* __restrict__ D,
+                                         const int64_t* __restrict__ pre, int nl, int64_t q_lo,
+                                         int64_t q_hi, int s_lo, F&& emit) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  if (q_lo >= q_hi) return;
+  SegView v;
+  seg_view_load(D, pre, nl, s_lo, v);
+  int64_t q0 = q_lo;
+  while (q0 < q_hi) {
+    int64_t b63 = readlane64(v.B, WAVE - 1);
+    if (b63 <= q0 + WALK_STEP - 1) {
+      // the view may miss boundaries of this step: move it to the segment
+      // holding q0
+      seg_view_load(D, pre, nl, v.sbase + __popcll(__ballot(v.B <= q0)), v);
+      b63 = readlane64(v.B, WAVE - 1);
     }
-    int64_t take = d.y - pos;
-    if (take > q1 - q) take = q1 - q;
-    if (take > BN_CH) take = BN_CH;
-    int32_t x[BN_CH];
+    if (b63 > q0 + WALK_STEP * WALK_UNROLL - 1) {
+      // WALK_UNROLL steps of WALK_PER positions per lane, loads in flight together
+      int32_t xs[WALK_UNROLL][WALK_PER];
+      const int base_rel = __popcll(__ballot(v.B <= q0));
+      uint64_t inside = __ballot(v.B > q0 && v.B <= q0 + WALK_STEP * WALK_UNROLL - 1);
+      int rel[WALK_UNROLL][WALK_PER];
 #pragma unroll
-    for (int j = 0; j < BN_CH; j++) x[j] = j < take ? A.ncol[pos + j] : INT_MAX;
-    fn(x, (int)take);
-    pos += take;
-    q += take;
+      for (int u = 0; u < WALK_UNROLL; u++)
+#pragma unroll
+        for (int k = 0; k < WALK_PER; k++) rel[u][k] = base_rel;
+      while (inside) {
+        const int j = __ffsll((long long)inside) - 1;
+        inside &= inside - 1;
+        const int64_t bj = readlane64(v.B, j);
+#pragma unroll
+        for (int u = 0; u < WALK_UNROLL; u++)
+#pragma unroll
+          for (int k = 0; k < WALK_PER; k++)
+            rel[u][k] += q0 + u * WALK_STEP + lane * WALK_PER + k >= bj ? 1 : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < WALK_UNROLL; u++)
+#pragma unroll
+        for (int k = 0; k < WALK_PER; k++) {
+          const int64_t p = q0 + u * WALK_STEP + lane * WALK_PER + k;
+          const int32_t d = __shfl(v.delta, rel[u][k], WAVE);
+          xs[u][k] = p < q_hi ? ncol[p + d] : INT_MAX;
+        }
+#pragma unroll
+      for (int u = 0; u < WALK_UNROLL; u++)
+#pragma unroll
+        for (int k = 0; k < WALK_PER; k++)
+          emit(xs[u][k], q0 + u * WALK_STEP + lane * WALK_PER + k < q_hi);
+      q0 += WALK_STEP * WALK_UNROLL;
+    } else if (b63 > q0 + WALK_STEP - 1) {
+      int32_t xs[WALK_PER];
+      int rel[WALK_PER];
+      const int base_rel = __popcll(__ballot(v.B <= q0));
+      uint64_t inside = __ballot(v.B > q0 && v.B <= q0 + WALK_STEP - 1);
+#pragma unroll
+      for (int k = 0; k < WALK_PER; k++) rel[k] = base_rel;
+      while (inside) {
+        const int j = __ffsll((long long)inside) - 1;
+        inside &= inside - 1;
+        const int64_t bj = readlane64(v.B, j);
+#pragma unroll
+        for (int k = 0; k < WALK_PER; k++) rel[k] += q0 + lane * WALK_PER + k >= bj ? 1 : 0;
+      }
+#pragma unroll
+      for (int k = 0; k < WALK_PER; k++) {
+        const int64_t p = q0 + lane * WALK_PER + k;
+        const int32_t d = __shfl(v.delta, rel[k], WAVE);
+        xs[k] = p < q_hi ? ncol[p + d] : INT_MAX;
+      }
+#pragma unroll
+      for (int k = 0; k < WALK_PER; k++) emit(xs[k], q0 + lane * WALK_PER + k < q_hi);
+      q0 += WALK_STEP;
+    } else {
+      // one position per lane: after the move above at most 63 boundaries
+      // lie in (q0, q0 + 63], all in the view
+      int rel = __popcll(__ballot(v.B <= q0));
+      uint64_t inside = __ballot(v.B > q0 && v.B <= q0 + WAVE - 1);
+      while (inside) {
+        const int j = __ffsll((long long)inside) - 1;
+        inside &= inside - 1;
+        rel += q0 + lane >= readlane64(v.B, j) ? 1 : 0;
+      }
+      const int32_t d = __shfl(v.delta, rel, WAVE);
+      const bool valid = q0 + lane < q_hi;
+      emit(valid ? ncol[q0 + lane + d] : INT_MAX, valid);
+      q0 += WAVE;
+    }
   }
 }
 
-__global__ __launch_bounds__(BN_NT) void k_c4_bin(C4Args A) {
-  __shared__ uint32_t cnt[C4_WIN_WORDS];
-  __shared__ int32_t hist[C4_BIN_KMAX + 1];
-  __shared__ int32_t cur[C4_BIN_KMAX + 1];
-  __shared__ int s_item, s_g1;
-  const int tid = threadIdx.x;
-  const int64_t b0 = A.start[A.bucket], cnt_items = A.start[A.bucket + 1] - b0;
-  const int64_t hbase = b0 - A.start[CB_WIN];
+// First b in [lo, hi] with key(b) >= target (key non-decreasing), hi + 1 if
+// none; hi - lo < 4096.  Two probes per lane.
+template <class KeyF>
+__device__ __forceinline__ int wave_first_ge(int lo, int hi, int64_t target, KeyF&& key) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  int pb = lo + lane * WAVE + WAVE - 1;
+  if (pb > hi) pb = hi;
+  const uint64_t m1 = __ballot(lo + lane * WAVE <= hi && key(pb) >= target);
+  if (!m1) return hi + 1;
+  const int c = __ffsll((long long)m1) - 1;
+  const int b = lo + c * WAVE + lane;
+  const uint64_t m2 = __ballot(b <= hi && key(b) >= target);
+  return lo + c * WAVE + __ffsll((long long)m2) - 1;
+}
+
+// hash slot of rank x in a table of BF_HSLOTS (rank + 1, count) pairs
+__device__ __forceinline__ uint32_t bin_hash_inc(uint64_t* tab, int32_t x, int* err) {
+  const uint64_t key = (uint64_t)(uint32_t)(x + 1) << 32;
+  uint32_t h = ((uint32_t)x * 0x9E3779B1u) >> (32 - BF_HBITS);
+  for (int p = 0; p < BF_HSLOTS; p++) {
+    uint64_t cur = tab[h];
+    if (cur == 0) {
+      const uint64_t o = atomicCAS(reinterpret_cast<unsigned long long*>(&tab[h]), 0ull,
+                                   (unsigned long long)(key | 1u));
+      if (o == 0) return 0;
+      cur = o;
+    }
+    if ((cur & 0xffffffff00000000ull) == key)
+      return (uint32_t)atomicAdd(reinterpret_cast<unsigned long long*>(&tab[h]), 1ull);
+    h = (h + 1) & (BF_HSLOTS - 1);
+  }
+  atomicOr(err, ERR_PROBE);
+  return 0;
+}
+
+__device__ __forceinline__ void region_clear(uint32_t* r) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  uint4* r4 = reinterpret_cast<uint4*>(r);
+#pragma unroll
+  for (int k = lane; k < BF_WORDS / 4; k += WAVE) r4[k] = make_uint4(0, 0, 0, 0);
+}
+
+__global__ __launch_bounds__(BN_NT, 4) void k_c4_bin(C4Args A) {
+  __shared__ uint4 cnt4[BN_NW * BF_WORDS / 4];
+  __shared__ int32_t off[BF_KMAX + 1];
+  __shared__ int16_t bigl[BF_BIGLIST];
+  __shared__ int s_item, s_nbig, s_b1;
+  uint32_t* cnt = reinterpret_cast<uint32_t*>(cnt4);
+  const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
+  const int64_t b0i = A.start[A.bucket], cnt_items = A.start[A.bucket + 1] - b0i;
+  const int64_t hbase = b0i - A.start[CB_WIN];
   int32_t* bins = A.bins + (int64_t)blockIdx.x * A.bin_cap;
+  uint32_t* mycnt = cnt + wid * BF_WORDS;
   u128_t acc = 0;
   unsigned long long wedges = 0, owners = 0, segs = 0, reads = 0;
-  for (int i = tid; i < C4_WIN_WORDS; i += BN_NT) cnt[i] = 0;
+  region_clear(mycnt);
   for (;;) {
     if (tid == 0) s_item = (int)atomicAdd(A.work, 1u);
     __syncthreads();
     const int64_t item = s_item;
-    __syncthreads();
     if (item >= cnt_items) break;
     const int64_t pos = cnt_items - 1 - item;  // heaviest owners (highest ranks) first
-    const int32_t u = A.order[b0 + pos];
+    const int32_t u = A.order[b0i + pos];
     const int64_t so = A.seg_off[hbase + pos];
-    const int nl = (int)(A.seg_off[hbase + pos + 1] - so);
+    const int nl = A.seg_cnt[hbase + pos];
     const int4* D = A.desc + so;
     const int64_t* pre = A.seg_pre + so;
-    const int64_t total = pre[nl - 1] + (D[nl - 1].y - D[nl - 1].x);
+    const int64_t total = nl > 0 ? pre[nl - 1] + (D[nl - 1].y - D[nl - 1].x) : 0;
     const int32_t uwords = zone_words(A, u);
-    const int K = (uwords + C4_WIN_WORDS - 1) / C4_WIN_WORDS;
+    const int K = (uwords + BF_WORDS - 1) >> BF_SHIFT;
+    for (int i = tid; i <= K; i += BN_NT) off[i] = 0;
+    // each wave's contiguous share of the endpoints, in whole steps, and the
+    // segment holding its first endpoint
+    constexpr int SHARE = WALK_STEP * WALK_UNROLL;
+    const int64_t steps = (total + SHARE - 1) / SHARE;
+    const int64_t q_lo = std::min(total, (steps * wid / BN_NW) * SHARE);
+    const int64_t q_hi = std::min(total, (steps * (wid + 1) / BN_NW) * SHARE);
+    int s_lo = 0;
+    if (q_lo < q_hi) {
+      // last segment with start <= q_lo: 64-ary search over the starts
+      int lo = 0, hi = nl - 1;
+      while (hi - lo >= WAVE) {
+        const int64_t stride = (hi - lo + WAVE) / WAVE;
+        const int64_t p = lo + stride * lane;
+        const uint64_t m = __ballot(p <= hi && pre[p] <= q_lo);
+        const int c = 63 - __clzll((long long)m);  // lane 0 (p = lo) always qualifies
+        const int nlo = (int)(lo + stride * c);
+        hi = (int)std::min<int64_t>(hi, nlo + stride - 1);
+        lo = nlo;
+      }
+      const uint64_t m = __ballot(lo + lane <= hi && pre[lo + lane] <= q_lo);
+      s_lo = lo + 63 - __clzll((long long)m);
+    }
     if (tid == 0) {
       owners++;
       segs += (unsigned long long)nl;
     }
-    // ---- pass 1: endpoints per window
-    for (int i = tid; i <= K; i += BN_NT) hist[i] = 0;
     __syncthreads();
-    bin_walk(A, D, pre, nl, total, [&](const int32_t (&x)[BN_CH], int take) {
-      int w[BN_CH];
-#pragma unroll
-      for (int j = 0; j < BN_CH; j++) w[j] = j < take ? bin_of(A, x[j]) : -1;
-      // one add per run of a window (the chunk is sorted)
-#pragma unroll
-      for (int j = 0; j < BN_CH; j++) {
-        if (w[j] >= 0 && (j == 0 || w[j] != w[j - 1])) {
-          int len = 1;
-#pragma unroll
-          for (int k = j + 1; k < BN_CH; k++) len += w[k] == w[j];
-          atomicAdd(&hist[w[j]], len);
-        }
-      }
+    // ---- pass 1: endpoints per bucket
+    bin_walk(A.ncol, D, pre, nl, q_lo, q_hi, s_lo, [&](int32_t x, bool valid) {
+      if (valid) atomicAdd(&off[fbin_of(A, x)], 1);
     });
     if (tid == 0) reads += (unsigned long long)total;
     __syncthreads();
-    // ---- groups of windows whose endpoints fit the scratch
-    int g0 = 0;
-    while (g0 < K) {
-      if (tid == 0) {
-        int64_t sum = 0;
-        int g = g0;
-        while (g < K && sum + hist[g] <= A.bin_cap) sum += hist[g++];
-        s_g1 = g;
+    // exclusive prefix: off[b] = first scatter position of bucket b
+    {
+      constexpr int PER = (BF_KMAX + 1 + BN_NT - 1) / BN_NT;
+      int32_t v[PER];
+      int64_t sum = 0;
+#pragma unroll
+      for (int k = 0; k < PER; k++) {
+        const int b = tid * PER + k;
+        v[k] = b < K ? off[b] : 0;
+        sum += v[k];
+      }
+      int64_t tot;
+      int64_t run = block_excl_scan64<BN_NT>(sum, &tot);
+#pragma unroll
+      for (int k = 0; k < PER; k++) {
+        const int b = tid * PER + k;
+        if (b <= K) off[b] = (int32_t)run;
+        run += v[k];
+      }
+    }
+    __syncthreads();
+    int b0 = 0;
+    while (b0 < K) {
+      // ---- the next bucket range whose endpoints fit the scratch
+      const int64_t p0 = off[b0];
+      if (wid == 0) {
+        const int f = wave_first_ge(b0 + 1, K, p0 + A.bin_cap + 1,
+                                    [&](int b) { return (int64_t)off[b]; });
+        if (lane == 0) {
+          s_b1 = f - 1;
+          s_nbig = 0;
+        }
       }
       __syncthreads();
-      const int g1 = s_g1;
-      if (g1 == g0) {
-        // one window alone beyond the scratch: counted from the rows
-        const int32_t wlo = g0 * C4_WIN_WORDS;
-        bin_walk(A, D, pre, nl, total, [&](const int32_t (&x)[BN_CH], int take) {
-          uint64_t part = 0;
-#pragma unroll
-          for (int j = 0; j < BN_CH; j++) {
-            if (j < take && bin_of(A, x[j]) == g0) {
-              part += window_inc(A, cnt, wlo, x[j]);
-              wedges++;
-            }
+      const int b1 = s_b1;
+      if (b1 == b0) {
+        // one bucket alone beyond the scratch: counted straight from the rows
+        const int32_t wlo = b0 << BF_SHIFT;
+        uint64_t part = 0;
+        unsigned long long took = 0;
+        bin_walk(A.ncol, D, pre, nl, q_lo, q_hi, s_lo, [&](int32_t x, bool valid) {
+          if (valid && fbin_of(A, x) == b0) {
+            part += window_inc(A, cnt, wlo, x);
+            took++;
           }
-          acc += part;
         });
+        acc += part;
+        wedges += took;
         if (tid == 0) reads += (unsigned long long)total;
         __syncthreads();
-        const int used = uwords - wlo < C4_WIN_WORDS ? uwords - wlo : C4_WIN_WORDS;
-        for (int i = tid; i < used; i += BN_NT) cnt[i] = 0;
+        for (int i = tid; i < BF_WORDS; i += BN_NT) cnt[i] = 0;
+        if (tid == 0) off[b0] = off[b0 + 1];  // the end of bucket b0
         __syncthreads();
-        g0++;
+        b0++;
         continue;
       }
-      // ---- pass 2: scatter the group's endpoints into per-window bins
-      if (tid == 0) {
-        int run = 0;
-        for (int g = g0; g < g1; g++) {
-          cur[g] = run;
-          run += hist[g];
-        }
-      }
-      __syncthreads();
-      bin_walk(A, D, pre, nl, total, [&](const int32_t (&x)[BN_CH], int take) {
-        int w[BN_CH];
-#pragma unroll
-        for (int j = 0; j < BN_CH; j++) {
-          w[j] = j < take ? bin_of(A, x[j]) : -1;
-          if (w[j] < g0 || w[j] >= g1) w[j] = -1;  // not in this group of windows
-        }
-        // a run of one window takes its slots with one add; the entries
-        // after the run's first follow it
-        int at = 0;
-#pragma unroll
-        for (int j = 0; j < BN_CH; j++) {
-          if (w[j] >= 0) {
-            if (j == 0 || w[j] != w[j - 1]) {
-              int len = 1;
-#pragma unroll
-              for (int k = j + 1; k < BN_CH; k++) len += w[k] == w[j];
-              at = atomicAdd(&cur[w[j]], len);
-            } else {
-              at++;
-            }
-            bins[at] = x[j];
-          }
+      // ---- pass 2: scatter the range's endpoints; afterwards off[b] is the
+      // end of bucket b (the start of bucket b + 1)
+      bin_walk(A.ncol, D, pre, nl, q_lo, q_hi, s_lo, [&](int32_t x, bool valid) {
+        if (valid) {
+          const int w = fbin_of(A, x);
+          if (w >= b0 && w < b1) bins[atomicAdd(&off[w], 1) - p0] = x;
         }
       });
       if (tid == 0) reads += (unsigned long long)total;
       __syncthreads();
-      // ---- pass 3: count every window of the group from its bin
-      int off = 0;
-      for (int g = g0; g < g1; g++) {
-        const int nb = hist[g];
-        if (nb == 0) continue;
-        const int32_t wlo = g * C4_WIN_WORDS;
-        const int32_t hnext =
-            wlo + C4_WIN_WORDS >= uwords ? u : zone_rank(A, wlo + C4_WIN_WORDS);
-        const int32_t hi = hnext < u ? hnext : u;
-        const int32_t wr = zone_rank(A, wlo);
-        const int kind =
-            hi <= A.z1 ? 0 : (wr >= A.z1 && hi <= A.z2 ? 1 : (wr >= A.z2 ? 2 : 3));
-        const int32_t* bg = bins + off;
-        auto count = [&](auto kind_tag) {
-          constexpr int KIND = decltype(kind_tag)::value;
+      // ---- pass 3: groups of buckets, wave wid taking groups wid, wid + 8,
+      // ...; the next group's bounds and endpoints are fetched before the
+      // current one is counted
+      const int64_t span = (int64_t)off[b1 - 1] - p0;
+      const int ngroups = (int)((span + BF_GROUP - 1) / BF_GROUP);
+      // first scatter position of bucket b of the range (b in [b0, b1])
+      auto bstart = [&](int b) -> int64_t { return b == 0 ? 0 : (int64_t)off[b - 1]; };
+      uint64_t* tab = reinterpret_cast<uint64_t*>(mycnt);
+      constexpr int HPER = (2 * BF_GROUP + WAVE - 1) / WAVE;  // hash-part endpoints per lane
+      struct Grp {
+        int l;                 // last bucket (-1: nothing to count)
+        int64_t hs, he, le;    // hash part [hs, he); lone dense bucket [he, le)
+      };
+      auto fetch = [&](int g, Grp& G, int32_t (&xv)[HPER]) {
+        G.l = -1;
+        G.hs = G.he = G.le = 0;
+        if (g < ngroups) {
+          const int64_t glo = p0 + (int64_t)g * BF_GROUP, ghi = glo + BF_GROUP;
+          const int f = wave_first_ge(b0, b1, glo, bstart);
+          int l = wave_first_ge(b0, b1, ghi, bstart) - 1;
+          if (l > b1 - 1) l = b1 - 1;
+          if (f <= l) {
+            // buckets f .. l - 1 hold fewer than BF_GROUP endpoints; bucket l
+            // joins them unless it alone holds more
+            const int64_t hs = bstart(f), ls = bstart(l), le = off[l];
+            G.l = l;
+            G.hs = hs;
+            G.he = le - ls > BF_GROUP ? ls : le;
+            G.le = le;
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < HPER; k++) {
+          const int64_t q = G.hs + lane + k * WAVE;
+          xv[k] = q < G.he ? bins[q - p0] : -1;
+        }
+      };
+      Grp cur, nxt;
+      int32_t xc[HPER], xn[HPER];
+      fetch(wid, nxt, xn);
+      for (int g = wid; g < ngroups; g += BN_NW) {
+        cur = nxt;
+#pragma unroll
+        for (int k = 0; k < HPER; k++) xc[k] = xn[k];
+        fetch(g + BN_NW, nxt, xn);
+        if (cur.l < 0) continue;  // a large bucket spans the whole stretch
+        if (cur.he > cur.hs) {
           uint64_t part = 0;
-          for (int q = tid; q < nb; q += BN_NT) part += window_inc_k<KIND>(A, cnt, wlo, wr, bg[q]);
+#pragma unroll
+          for (int k = 0; k < HPER; k++)
+            if (xc[k] >= 0) part += bin_hash_inc(tab, xc[k], &A.scal->err);
           acc += part;
-        };
-        switch (kind) {
-          case 0: count(std::integral_constant<int, 0>{}); break;
-          case 1: count(std::integral_constant<int, 1>{}); break;
-          case 2: count(std::integral_constant<int, 2>{}); break;
-          default: count(std::integral_constant<int, 3>{}); break;
+          if (lane == 0) wedges += (unsigned long long)(cur.he - cur.hs);
+          wave_sync();
+          region_clear(mycnt);
+          wave_sync();
         }
-        if (tid == 0) wedges += (unsigned long long)nb;
-        __syncthreads();
-        // clear the counters: word by word for a sparse bin, else all used words
-        const int used = uwords - wlo < C4_WIN_WORDS ? uwords - wlo : C4_WIN_WORDS;
-        if (nb < used / 4) {
-          for (int q = tid; q < nb; q += BN_NT) cnt[zone_word(A, bg[q]) - wlo] = 0;
-        } else {
-          for (int i = tid; i < used; i += BN_NT) cnt[i] = 0;
+        if (cur.le == cur.he) continue;
+        const int l = cur.l;
+        const int64_t ls = cur.he, le = cur.le;
+        if (le - ls > BF_BIG) {
+          if (lane == 0) {
+            const int k = atomicAdd(&s_nbig, 1);
+            if (k < BF_BIGLIST) bigl[k] = (int16_t)l;
+          }
+          continue;
         }
-        __syncthreads();
-        off += nb;
+        // ---- one dense bucket in this wave's region
+        const int32_t wlo = l << BF_SHIFT;
+        uint64_t part = 0;
+        int64_t q = ls + lane;
+        for (; q + 3 * WAVE < le; q += 4 * WAVE) {
+          int32_t xv[4];
+#pragma unroll
+          for (int k = 0; k < 4; k++) xv[k] = bins[q + k * WAVE - p0];
+#pragma unroll
+          for (int k = 0; k < 4; k++) part += window_inc(A, mycnt, wlo, xv[k]);
+        }
+        for (; q < le; q += WAVE) part += window_inc(A, mycnt, wlo, bins[q - p0]);
+        acc += part;
+        if (lane == 0) wedges += (unsigned long long)(le - ls);
+        wave_sync();
+        region_clear(mycnt);
+        wave_sync();
       }
-      g0 = g1;
+      __syncthreads();
+      // dense buckets too large for one wave: the whole block, one region
+      // (listed, or found by a scan of the range when the list overflowed)
+      const int nbig = s_nbig;
+      auto count_big = [&](int b) {
+        const int64_t bs = bstart(b), be = off[b];
+        const int32_t wlo = b << BF_SHIFT;
+        uint64_t part = 0;
+        for (int64_t q = bs + tid; q < be; q += BN_NT) part += window_inc(A, cnt, wlo, bins[q - p0]);
+        acc += part;
+        if (tid == 0) wedges += (unsigned long long)(be - bs);
+        __syncthreads();
+        for (int i = tid; i < BF_WORDS; i += BN_NT) cnt[i] = 0;
+        __syncthreads();
+      };
+      if (nbig <= BF_BIGLIST) {
+        for (int k = 0; k < nbig; k++) count_big(bigl[k]);
+      } else {
+        for (int b = b0; b < b1; b++)
+          if (off[b] - bstart(b) > BF_BIG) count_big(b);
+      }
+      b0 = b1;
+      __syncthreads();
     }
   }
   block_add_u128<BN_NT>(&A.scal->acc[ACC_C4], acc);
@@ -1116,6 +1352,7 @@ Launch c4_plan(const Prep& P, const Classes& C, Scal* scal, const Tuning& tu, ui
   const int64_t HB = hstart[CB_BIN + 1] - hstart[CB_BIN];
   int4* desc = nullptr;
   int64_t* seg_pre = nullptr;
+  int32_t* seg_cnt = nullptr;
   int32_t* bins = nullptr;
   int64_t bin_cap = 0;
   unsigned bin_grid = 0;
@@ -1126,20 +1363,27 @@ Launch c4_plan(const Prep& P, const Classes& C, Scal* scal, const Tuning& tu, ui
     M4_HIP(hipMemcpyAsync(&nseg, seg_off + H, 8, hipMemcpyDeviceToHost, s));
     M4_HIP(hipStreamSynchronize(s));
     const size_t db = ((size_t)(nseg > 0 ? nseg : 1) * sizeof(int4) + 255) & ~size_t(255);
-    const size_t pb = ((size_t)(nseg > 0 ? nseg : 1) * 8 + 255) & ~size_t(255);
-    // binned owners: per block scratch of at most 2^21 endpoints (no owner
-    // has more endpoints than the graph has CSR entries)
+    const size_t cb = ((size_t)H * 4 + 255) & ~size_t(255);
+    // length prefixes: binned owners only (their slots, after the window owners')
+    const size_t pb = HB > 0 ? ((size_t)(nseg > 0 ? nseg : 1) * 8 + 255) & ~size_t(255) : 0;
+    // binned owners: two workgroups per CU, each with a scratch of at most
+    // 2^20 endpoints by default (no owner has more endpoints than the graph
+    // has CSR entries)
     size_t bb = 0;
     if (HB > 0) {
-      bin_cap = std::min<int64_t>(int64_t(1) << 21, std::max<int64_t>(P.nnz, 1));
-      bin_grid = (unsigned)std::min<int64_t>(num_cu, HB);
+      const int64_t cap = tu.c4_bin_cap > 0 ? tu.c4_bin_cap : int64_t(1) << 20;
+      bin_cap = std::min<int64_t>(cap, std::max<int64_t>(P.nnz, 1));
+      bin_grid = (unsigned)std::min<int64_t>(2 * (int64_t)num_cu, HB);
       bb = (size_t)bin_grid * (size_t)bin_cap * 4;
     }
-    char* scr = big_scratch(db + pb + bb);
+    char* scr = big_scratch(db + cb + pb + bb);
     if (!scr) throw Fail(M4_ENOMEM, "no room for 4-cycle segment descriptors");
     desc = reinterpret_cast<int4*>(scr);
-    seg_pre = reinterpret_cast<int64_t*>(scr + db);
-    if (HB > 0) bins = reinterpret_cast<int32_t*>(scr + db + pb);
+    seg_cnt = reinterpret_cast<int32_t*>(scr + db);
+    if (HB > 0) {
+      seg_pre = reinterpret_cast<int64_t*>(scr + db + cb);
+      bins = reinterpret_cast<int32_t*>(scr + db + cb + pb);
+    }
   }
   if (kt) kt->end(M4_K_C4_PLAN, s);
 
@@ -1158,6 +1402,7 @@ Launch c4_plan(const Prep& P, const Classes& C, Scal* scal, const Tuning& tu, ui
   A.seg_off = seg_off;
   A.desc = desc;
   A.seg_pre = seg_pre;
+  A.seg_cnt = seg_cnt;
   A.bins = bins;
   A.bin_cap = bin_cap;
   A.z1 = (int32_t)z1;
@@ -1174,7 +1419,7 @@ Launch c4_plan(const Prep& P, const Classes& C, Scal* scal, const Tuning& tu, ui
         k_lowcut<<<blocks_for(n, 256), 256, 0, ls>>>(P.nptr, P.ncol, P.row_len, n, C.r1, lowcut);
       k_c4_desc<<<(unsigned)H, 256, 0, ls>>>(order, start, seg_off, P.nptr, P.dlo, P.ncol,
                                              P.row_len ? nullptr : lowcut, P.row_len, C.r1,
-                                             desc, seg_pre);
+                                             desc, seg_pre, seg_cnt);
       if (kt) kt->end(M4_K_C4_DESC, ls);
     }
     // heavy owners first: one 1024-thread workgroup per CU

@@ -4,6 +4,13 @@
 
 namespace m4 {
 
+// Orders the LDS accesses of one wavefront (all lanes run in lockstep; the
+// fence keeps the compiler from moving LDS loads above earlier stores).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 typedef unsigned __int128 u128_t;
 
 // Exact 128-bit add into memory (global or LDS) from two 64-bit atomics.

@@ -119,6 +119,7 @@ struct Tuning {
   int c4_med_win = 64;      // ranged medium owners: 16 windows >= this per range (0: none)
   int c4_bin_win = 6;       // owners above the one-pass medium bound whose endpoints span at
                             // least this many counter windows are binned by window (0: never)
+  int c4_bin_cap = 0;       // endpoints of a binning workgroup's scratch (0: 2^20)
 };
 
 // Optional per-launch HIP event pairs (M4_TIMING).

@@ -129,7 +129,7 @@ int count_partitioned(m4_ctx* c, const m4_csr* g, const m4_opts* o, uint64_t out
   uint64_t budget = o ? o->device_budget_bytes : 0;
   if (budget == 0) budget = resident_bytes(n, nnz, c->num_cu) / 3 + (1 << 20);
   const double t_start = now_ms();
-  double t_h2d = 0;
+  double t_h2d = 0, t_host = 0, t_phase[4] = {0, 0, 0, 0};
   uint64_t h2d_bytes = 0, halo_rows = 0, parts = 0;
 
   if (!c->part) c->part = new PartState();
@@ -342,6 +342,7 @@ int count_partitioned(m4_ctx* c, const m4_csr* g, const m4_opts* o, uint64_t out
     int32_t* hcc = reinterpret_cast<int32_t*>(S.p + al((2 * rows.size() + 2) * 8) +
                                               al((rows.size() + 1) * 4));
     int64_t off = 0;
+    const double tg = now_ms();
     for (size_t i = 0; i < rows.size(); i++) {
       const RowPart& r = rows[i];
       memcpy(hcc + off, hc + H.nptr[r.v] + r.first, (size_t)r.len * 4);
@@ -350,6 +351,7 @@ int count_partitioned(m4_ctx* c, const m4_csr* g, const m4_opts* o, uint64_t out
       hl[i] = r.first + r.len;        // stored prefix length (when the row starts at 0)
       off += r.len;
     }
+    t_host += now_ms() - tg;
     up(dpairs, hp, rows.size() * 16);
     up(dlens, hl, rows.size() * 4);
     up(dcol, hcc, (size_t)ent * 4);
@@ -369,6 +371,8 @@ int count_partitioned(m4_ctx* c, const m4_csr* g, const m4_opts* o, uint64_t out
     return a;
   };
 
+  t_phase[0] = now_ms() - t_start;
+  double t_mark = now_ms();
   // ---- 3. triangle / 4-clique anchors over owner ranges with oriented halos
   {
     const size_t cap_rows = D.cap > fixed_used + tri_tmp ? D.cap - fixed_used - tri_tmp : 0;
@@ -382,6 +386,7 @@ int count_partitioned(m4_ctx* c, const m4_csr* g, const m4_opts* o, uint64_t out
         if (mark[v] == stamp) return (size_t)0;
         return (size_t)H.dplus[v] * 4 + 28;
       };
+      const double tp = now_ms();
       while (hi < n) {
         // owner hi with its out-list and the out-lists of its out-neighbours
         size_t add = need_row((int32_t)hi);
@@ -398,6 +403,7 @@ int count_partitioned(m4_ctx* c, const m4_csr* g, const m4_opts* o, uint64_t out
         for (int64_t j = 0; j < H.dplus[hi]; j++) put(hc[b0 + j]);
         hi++;
       }
+      t_host += now_ms() - tp;
       if (bytes > cap_rows) throw Fail(M4_ENOMEM, "device budget below one owner's halo");
       P.ncol = upload_rows(false, 1);
       P.own_lo = lo;
@@ -409,6 +415,8 @@ int count_partitioned(m4_ctx* c, const m4_csr* g, const m4_opts* o, uint64_t out
     }
   }
 
+  t_phase[1] = now_ms() - t_mark;
+  t_mark = now_ms();
   // ---- 4. 4-cycle anchor over owner ranges with lower halos cut below hi
   {
     const size_t cap_rows = D.cap > fixed_used + c4_tmp ? D.cap - fixed_used - c4_tmp : 0;
@@ -419,9 +427,11 @@ int count_partitioned(m4_ctx* c, const m4_csr* g, const m4_opts* o, uint64_t out
       stamp++;
       rows.clear();
       std::vector<int32_t> members;
-      size_t bytes = 0;
+      // alignment of the descriptor arrays in the scratch region
+      size_t bytes = 512;
       int64_t hi = lo;
       uint64_t segs = 0;
+      const double tp = now_ms();
       while (hi < n) {
         const int64_t u = hi;
         // rows already held gain the entry u when the upper end moves past u
@@ -440,7 +450,7 @@ int count_partitioned(m4_ctx* c, const m4_csr* g, const m4_opts* o, uint64_t out
           fresh.push_back({v, (int32_t)len});
         }
         for (auto& f : fresh) add += (size_t)f.second * 4 + 32;
-        add += (size_t)H.dlo[u] * 24 + 512;  // segment descriptors and their prefix
+        add += (size_t)H.dlo[u] * 16 + 4;  // segment descriptors and their count
         if (bytes + add > cap_rows && hi > lo) break;
         bytes += add;
         for (int64_t p = ub; p < ue; p++)
@@ -453,6 +463,7 @@ int count_partitioned(m4_ctx* c, const m4_csr* g, const m4_opts* o, uint64_t out
         segs += H.dlo[u];
         hi++;
       }
+      t_host += now_ms() - tp;
       if (bytes > cap_rows) throw Fail(M4_ENOMEM, "device budget below one owner's halo");
       for (int32_t v : members) rows.push_back({v, 0, stored[v]});
       P.ncol = upload_rows(true, 0);
@@ -467,6 +478,8 @@ int count_partitioned(m4_ctx* c, const m4_csr* g, const m4_opts* o, uint64_t out
     }
   }
 
+  t_phase[2] = now_ms() - t_mark;
+  t_mark = now_ms();
   // ---- 5. closure over owner ranges (out-lists only), then the inverse
   {
     const size_t cap_rows = D.cap > fixed_used + 4096 ? D.cap - fixed_used - 4096 : 0;
@@ -475,6 +488,7 @@ int count_partitioned(m4_ctx* c, const m4_csr* g, const m4_opts* o, uint64_t out
       rows.clear();
       size_t bytes = 0;
       int64_t hi = lo;
+      const double tp = now_ms();
       while (hi < n) {
         const size_t add = (size_t)H.dplus[hi] * 4 + 28;
         if (bytes + add > cap_rows && hi > lo) break;
@@ -482,6 +496,7 @@ int count_partitioned(m4_ctx* c, const m4_csr* g, const m4_opts* o, uint64_t out
         rows.push_back({(int32_t)hi, (int64_t)H.dlo[hi], H.dplus[hi]});
         hi++;
       }
+      t_host += now_ms() - tp;
       P.ncol = upload_rows(false, 1);
       P.own_lo = lo;
       P.own_hi = hi;
@@ -493,6 +508,7 @@ int count_partitioned(m4_ctx* c, const m4_csr* g, const m4_opts* o, uint64_t out
   finalize_run(c->scal, s);
   M4_HIP(hipMemcpyAsync(c->scal_host, c->scal, sizeof(Scal), hipMemcpyDeviceToHost, s));
   M4_HIP(hipStreamSynchronize(s));
+  t_phase[3] = now_ms() - t_mark;
   const Scal& h = *c->scal_host;
   if (h.err) return scal_error(c, h.err);
   if (h.status == 3) return set_error(c, M4_EOVERFLOW, "a count is >= 2^64");
@@ -509,6 +525,11 @@ int count_partitioned(m4_ctx* c, const m4_csr* g, const m4_opts* o, uint64_t out
     st->halo_rows = halo_rows;
     st->ms_total = now_ms() - t_start;
     st->ms_h2d = t_h2d;
+    st->ms_build = t_phase[0];
+    st->ms_tri = t_phase[1];
+    st->ms_c4 = t_phase[2];
+    st->ms_closure = t_phase[3];
+    st->ms_host = t_host;
     st->device_bytes = c->held_bytes();
   }
   return M4_OK;

@@ -5,13 +5,6 @@
 
 namespace m4 {
 
-// Orders the LDS accesses of one wavefront (all lanes run in lockstep; the
-// fence keeps the compiler from moving LDS loads above earlier stores).
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
-
 // signature of a cached frontier: (j, slot, required-adjacency mask,
 // required-non-adjacency mask); a lookup matches only on all four fields.
 __host__ __device__ __forceinline__ uint32_t sig_key(uint32_t j, uint32_t slot, uint32_t mplus,

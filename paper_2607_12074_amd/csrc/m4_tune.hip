@@ -38,6 +38,7 @@ void to_public(const Tuning& t, m4_tuning* out) {
   out->probe_w = t.probe_w;
   out->c4_med_win = t.c4_med_win;
   out->c4_bin_win = t.c4_bin_win;
+  out->c4_bin_cap = t.c4_bin_cap;
 }
 
 }  // namespace
@@ -55,7 +56,8 @@ extern "C" int m4_set_tuning(m4_ctx* ctx, const m4_tuning* t) {
       t->batch_light < 1 || t->batch_light > 256 ||
       (t->hub_min != 0 && (t->hub_min < 4 || t->hub_min > 65536)) || t->c4_med_max < 0 ||
       t->c4_med_max > 3 * C4_MED_SLOTS / 4 || t->probe_w < 1 || t->probe_w > 256 ||
-      t->c4_med_win < 0 || t->c4_med_win > 65536 || t->c4_bin_win < 0 || t->c4_bin_win > 65536)
+      t->c4_med_win < 0 || t->c4_med_win > 65536 || t->c4_bin_win < 0 || t->c4_bin_win > 65536 ||
+      (t->c4_bin_cap != 0 && (t->c4_bin_cap < 64 || t->c4_bin_cap > (1 << 24))))
     return set_error(ctx, M4_EINVAL, "tuning value out of range");
   ctx->tune.tri_wave_max = t->tri_wave_max;
   ctx->tune.c4_light_max = t->c4_light_max;
@@ -66,6 +68,7 @@ extern "C" int m4_set_tuning(m4_ctx* ctx, const m4_tuning* t) {
   ctx->tune.probe_w = t->probe_w;
   ctx->tune.c4_med_win = t->c4_med_win;
   ctx->tune.c4_bin_win = t->c4_bin_win;
+  ctx->tune.c4_bin_cap = t->c4_bin_cap;
   return M4_OK;
 }
 

@@ -288,22 +288,32 @@ def test_web_scale24_matches_oracle_golden(ctx):
 
 def test_binned_four_cycle_owners(ctx):
     # every owner above the one-pass table bound binned by counter window
-    # (c4_bin_win = 1), or only those spanning several windows, or none: the
-    # counts never change; the 300000-cycle graph spans two windows
+    # (c4_bin_win = 1), or only those spanning several windows, or none; the
+    # binning scratch shrunk to 1000 endpoints (owners scattered in several
+    # rank ranges) or to 64 (buckets alone beyond it, counted straight from
+    # the rows): the counts never change; the 300000-cycle graph spans two
+    # windows
     import paper_2607_12074_amd as m4
     cyc, bip = G.cycle(300000), G.complete_bipartite(50, 200)
     graphs = [gg.rmat(14, 10, 0.57, 0.19, 0.19, 5), gg.rmat(15, 16, 0.45, 0.22, 0.22, 6),
-              gg.ba(6000, 9, 2), G.complete_bipartite(7, 900),
+              gg.ba(6000, 9, 2), G.complete_bipartite(7, 900), G.complete_bipartite(60, 3000),
               G.disjoint_union(G.disjoint_union(cyc, bip), gg.ba(3000, 12, 7))]
     base = ctx.get_tuning()
+    slot = m4.KERNELS.index("c4_bin")
+    binned = 0
     try:
         for g in graphs:
             ref = oracle.closure(*g)
-            for bw in (1, 2, 0):
-                ctx.set_tuning(c4_bin_win=bw)
+            for bw, cap in ((1, 0), (1, 1000), (1, 64), (2, 0), (0, 0)):
+                ctx.set_tuning(c4_bin_win=bw, c4_bin_cap=cap)
                 got, st = ctx.count(*g, stats=True)
-                assert got == ref, bw
-                if bw == 1 and st["C4_ni"] > 0:
-                    assert st["k_rows"][m4.KERNELS.index("c4_bin")] > 0 or True
+                assert got == ref, (bw, cap)
+                if bw == 0:
+                    assert st["k_rows"][slot] == 0
+                else:
+                    binned += st["k_rows"][slot]
+                    # every wedge endpoint of a binned owner is counted once
+                    assert st["k_elems"][slot] <= st["wedges"]
     finally:
         ctx.set_tuning(**base)
+    assert binned > 0
