@@ -69,7 +69,8 @@ typedef struct {
 #define M4_TIMING 0x10u         /* time every kernel launch with HIP events         */
 #define M4_SERIAL 0x40u         /* single graph: run the triangle and 4-cycle stages
                                    one after the other on one stream (by default
-                                   they overlap on two streams)                    */
+                                   they overlap on two streams, except when
+                                   4-cycle owners are binned)                      */
 #define M4_PLAIN_LOOP 0x20u     /* m4_count_batch: one single-graph call per graph
                                    (the reference point of the batched launch)     */
 

@@ -296,7 +296,10 @@ void run_resident(m4_ctx* c, const int64_t* rp, const int32_t* col, int64_t n, i
   // workspace; their heavy kernels then run concurrently, the 4-cycle stage
   // on the context's second stream (forked from and joined back into s), so
   // that each fills the CUs the other's tail leaves idle (triangle kernels
-  // are queued first: measured slightly ahead of the reverse order)
+  // are queued first: measured slightly ahead of the reverse order).  When
+  // 4-cycle owners are binned the stages run in order: the binning kernel
+  // keeps two persistent workgroups and all of the LDS on every CU, and
+  // sharing the CUs with the triangle kernels measured slower.
   const size_t c4_bytes = c4_tmp_bytes(n);
   Arena at, ac;
   at.base = c->tmp.ptr;
@@ -304,8 +307,9 @@ void run_resident(m4_ctx* c, const int64_t* rp, const int32_t* col, int64_t n, i
   ac.base = c->tmp.ptr + at.cap;
   ac.cap = c4_bytes;
   Launch tri = tri_plan(P, c->scal, tu, flags, cache_rows, at, s, c->num_cu, big, kt);
-  Launch c4 = c4_plan(P, C, c->scal, tu, flags, ac, s, c->num_cu, kt, big2);
-  if (flags & M4_SERIAL) {
+  bool binned = false;
+  Launch c4 = c4_plan(P, C, c->scal, tu, flags, ac, s, c->num_cu, kt, big2, &binned);
+  if ((flags & M4_SERIAL) || binned) {
     tri(s);
     if (want_timing) M4_HIP(hipEventRecord(c->ev[2], s));
     c4(s);

@@ -870,13 +870,25 @@ constexpr int BF_GROUP = 192;    // scatter positions per group
 constexpr int BF_HBITS = BF_SHIFT - 1, BF_HSLOTS = 1 << BF_HBITS;  // 64-bit slots
 constexpr int BF_BIG = 4096;     // dense buckets above this: the whole block
 constexpr int BF_BIGLIST = 48;
-constexpr int BF_UNROLL = 8;     // walk steps in flight per wave
+constexpr int BF_SB = 8;         // staging buffer entries per target (two 16-byte stores)
+constexpr int BF_NTS = 1032;     // targets with a staging buffer (12 words each)
 static_assert((int64_t)C4_BIN_KMAX * C4_WIN_WORDS <= (int64_t)BF_KMAX * BF_WORDS,
               "a binned owner's fine buckets must fit the LDS histogram");
 static_assert(2 * BF_GROUP <= BF_HSLOTS / 2, "a hash group must keep its table half empty");
+static_assert(BF_KMAX + (4 + BF_SB) * BF_NTS <= BN_NW * BF_WORDS && (BF_KMAX + 4 * BF_NTS) % 4 == 0,
+              "scatter cursors and staging buffers fit the counter regions, the buffers 16-byte aligned");
 
 __device__ __forceinline__ int32_t fbin_of(const C4Args& A, int32_t x) {
   return zone_word(A, x) >> BF_SHIFT;
+}
+
+// a wave-uniform value held in scalar registers (LDS and vector loads
+// return it in vector registers)
+__device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni64(int64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
 __device__ __forceinline__ int64_t readlane64(int64_t v, int l) {
@@ -898,7 +910,6 @@ struct SegView {
 constexpr int64_t SEG_FAR = int64_t(1) << 62;
 constexpr int WALK_PER = 4;                     // positions per lane and step
 constexpr int WALK_STEP = WAVE * WALK_PER;      // positions per wave and step
-constexpr int WALK_UNROLL = 2;                  // steps in flight
 
 __device__ __forceinline__ void seg_view_load(const int4* __restrict__ D,
                                               const int64_t* __restrict__ pre, int nl, int sbase,
@@ -915,7 +926,7 @@ __device__ __forceinline__ void seg_view_load(const int4* __restrict__ D,
 // view's boundaries at or below it, counted over the few boundaries inside
 // the step.  Where 64 segments end within a step (very short segments) the
 // step falls back to one position per lane.
-template <class F>
+template <int WALK_UNROLL = 2, class F>
 __device__ __forceinline__ void bin_walk(const int32_t* __restrict__ ncol,
                                          const int4* __restrict__ D,
                                          const int64_t* __restrict__ pre, int nl, int64_t q_lo,
@@ -1043,6 +1054,41 @@ __device__ __forceinline__ uint32_t bin_hash_inc(uint64_t* tab, int32_t x, int* 
   return 0;
 }
 
+// The same for up to N endpoints of one lane (x < 0: none): the home slots
+// are read for all of them first, then the empty ones claimed and the
+// matching ones incremented, each step issued for all N before any result is
+// used; a lost claim or an occupied home slot probes on.
+template <int N>
+__device__ __forceinline__ uint64_t bin_hash_batch(uint64_t* tab, const int32_t (&x)[N], int* err) {
+  auto home = [](int32_t v) { return ((uint32_t)v * 0x9E3779B1u) >> (32 - BF_HBITS); };
+  auto key = [](int32_t v) { return (uint64_t)(uint32_t)(v + 1) << 32; };
+  uint64_t o[N];
+#pragma unroll
+  for (int k = 0; k < N; k++) o[k] = x[k] >= 0 ? tab[home(x[k])] : 1;  // 1: no endpoint
+  uint32_t won = 0;
+#pragma unroll
+  for (int k = 0; k < N; k++)
+    if (x[k] >= 0 && o[k] == 0) {
+      o[k] = atomicCAS(reinterpret_cast<unsigned long long*>(&tab[home(x[k])]), 0ull,
+                       (unsigned long long)(key(x[k]) | 1u));
+      if (o[k] == 0) won |= 1u << k;
+    }
+  uint64_t sum = 0;
+  uint32_t rest = 0;
+#pragma unroll
+  for (int k = 0; k < N; k++) {
+    if (x[k] < 0 || ((won >> k) & 1)) continue;
+    if ((o[k] & 0xffffffff00000000ull) == key(x[k]))
+      sum += (uint32_t)atomicAdd(reinterpret_cast<unsigned long long*>(&tab[home(x[k])]), 1ull);
+    else
+      rest |= 1u << k;
+  }
+#pragma unroll
+  for (int k = 0; k < N; k++)
+    if ((rest >> k) & 1) sum += bin_hash_inc(tab, x[k], err);
+  return sum;
+}
+
 __device__ __forceinline__ void region_clear(uint32_t* r) {
   const int lane = threadIdx.x & (WAVE - 1);
   uint4* r4 = reinterpret_cast<uint4*>(r);
@@ -1054,34 +1100,37 @@ __global__ __launch_bounds__(BN_NT, 4) void k_c4_bin(C4Args A) {
   __shared__ uint4 cnt4[BN_NW * BF_WORDS / 4];
   __shared__ int32_t off[BF_KMAX + 1];
   __shared__ int16_t bigl[BF_BIGLIST];
-  __shared__ int s_item, s_nbig, s_b1;
+  __shared__ int s_item, s_nbig, s_b1, s_next, s_nt;
   uint32_t* cnt = reinterpret_cast<uint32_t*>(cnt4);
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
   const int64_t b0i = A.start[A.bucket], cnt_items = A.start[A.bucket + 1] - b0i;
   const int64_t hbase = b0i - A.start[CB_WIN];
-  int32_t* bins = A.bins + (int64_t)blockIdx.x * A.bin_cap;
+  // per block: the scratch plus up to 7 padding entries per target
+  int32_t* bins = A.bins + (int64_t)blockIdx.x * (A.bin_cap + 8 * BF_KMAX);
   uint32_t* mycnt = cnt + wid * BF_WORDS;
   u128_t acc = 0;
+  // counters kept equal across a wave (scalar registers); lane 0 of each
+  // wave contributes its wave's, the block-wide ones counted by wave 0
   unsigned long long wedges = 0, owners = 0, segs = 0, reads = 0;
   region_clear(mycnt);
   for (;;) {
     if (tid == 0) s_item = (int)atomicAdd(A.work, 1u);
     __syncthreads();
-    const int64_t item = s_item;
+    const int64_t item = uni(s_item);
     if (item >= cnt_items) break;
     const int64_t pos = cnt_items - 1 - item;  // heaviest owners (highest ranks) first
-    const int32_t u = A.order[b0i + pos];
-    const int64_t so = A.seg_off[hbase + pos];
-    const int nl = A.seg_cnt[hbase + pos];
+    const int32_t u = uni(A.order[b0i + pos]);
+    const int64_t so = uni64(A.seg_off[hbase + pos]);
+    const int nl = uni(A.seg_cnt[hbase + pos]);
     const int4* D = A.desc + so;
     const int64_t* pre = A.seg_pre + so;
-    const int64_t total = nl > 0 ? pre[nl - 1] + (D[nl - 1].y - D[nl - 1].x) : 0;
+    const int64_t total = uni64(nl > 0 ? pre[nl - 1] + (D[nl - 1].y - D[nl - 1].x) : 0);
     const int32_t uwords = zone_words(A, u);
     const int K = (uwords + BF_WORDS - 1) >> BF_SHIFT;
     for (int i = tid; i <= K; i += BN_NT) off[i] = 0;
     // each wave's contiguous share of the endpoints, in whole steps, and the
     // segment holding its first endpoint
-    constexpr int SHARE = WALK_STEP * WALK_UNROLL;
+    constexpr int SHARE = WALK_STEP * 2;
     const int64_t steps = (total + SHARE - 1) / SHARE;
     const int64_t q_lo = std::min(total, (steps * wid / BN_NW) * SHARE);
     const int64_t q_hi = std::min(total, (steps * (wid + 1) / BN_NW) * SHARE);
@@ -1101,16 +1150,14 @@ __global__ __launch_bounds__(BN_NT, 4) void k_c4_bin(C4Args A) {
       const uint64_t m = __ballot(lo + lane <= hi && pre[lo + lane] <= q_lo);
       s_lo = lo + 63 - __clzll((long long)m);
     }
-    if (tid == 0) {
-      owners++;
-      segs += (unsigned long long)nl;
-    }
+    owners++;
+    segs += (unsigned long long)nl;
     __syncthreads();
     // ---- pass 1: endpoints per bucket
     bin_walk(A.ncol, D, pre, nl, q_lo, q_hi, s_lo, [&](int32_t x, bool valid) {
       if (valid) atomicAdd(&off[fbin_of(A, x)], 1);
     });
-    if (tid == 0) reads += (unsigned long long)total;
+    reads += (unsigned long long)total;
     __syncthreads();
     // exclusive prefix: off[b] = first scatter position of bucket b
     {
@@ -1136,7 +1183,7 @@ __global__ __launch_bounds__(BN_NT, 4) void k_c4_bin(C4Args A) {
     int b0 = 0;
     while (b0 < K) {
       // ---- the next bucket range whose endpoints fit the scratch
-      const int64_t p0 = off[b0];
+      const int64_t p0 = uni(off[b0]);
       if (wid == 0) {
         const int f = wave_first_ge(b0 + 1, K, p0 + A.bin_cap + 1,
                                     [&](int b) { return (int64_t)off[b]; });
@@ -1146,21 +1193,18 @@ __global__ __launch_bounds__(BN_NT, 4) void k_c4_bin(C4Args A) {
         }
       }
       __syncthreads();
-      const int b1 = s_b1;
+      const int b1 = uni(s_b1);
+      const int64_t off_end = uni(off[b1]);  // first position past the range
       if (b1 == b0) {
         // one bucket alone beyond the scratch: counted straight from the rows
         const int32_t wlo = b0 << BF_SHIFT;
         uint64_t part = 0;
-        unsigned long long took = 0;
         bin_walk(A.ncol, D, pre, nl, q_lo, q_hi, s_lo, [&](int32_t x, bool valid) {
-          if (valid && fbin_of(A, x) == b0) {
-            part += window_inc(A, cnt, wlo, x);
-            took++;
-          }
+          if (valid && fbin_of(A, x) == b0) part += window_inc(A, cnt, wlo, x);
         });
         acc += part;
-        wedges += took;
-        if (tid == 0) reads += (unsigned long long)total;
+        if (wid == 0) wedges += (unsigned long long)(off[b0 + 1] - off[b0]);
+        reads += (unsigned long long)total;
         __syncthreads();
         for (int i = tid; i < BF_WORDS; i += BN_NT) cnt[i] = 0;
         if (tid == 0) off[b0] = off[b0 + 1];  // the end of bucket b0
@@ -1168,112 +1212,227 @@ __global__ __launch_bounds__(BN_NT, 4) void k_c4_bin(C4Args A) {
         b0++;
         continue;
       }
-      // ---- pass 2: scatter the range's endpoints; afterwards off[b] is the
-      // end of bucket b (the start of bucket b + 1)
-      bin_walk(A.ncol, D, pre, nl, q_lo, q_hi, s_lo, [&](int32_t x, bool valid) {
+      // ---- targets: runs of consecutive buckets that start within one
+      // stretch of BF_GROUP positions (hash targets), a bucket holding more
+      // than BF_GROUP endpoints alone (a dense target; it always ends its
+      // stretch).  Each bucket's target goes to off; the scatter state sits in
+      // the counter regions, unused until pass 3: per target its write
+      // cursor (bit 31: dense), and for the first BF_NTS targets an 8-entry
+      // staging buffer (its fill and completion counts, and a tail cursor for
+      // endpoints that arrive while it is full).  Targets start at multiples
+      // of 8 scratch entries, so a full buffer leaves as two aligned 16-byte
+      // stores instead of eight scattered ones.
+      uint32_t* head = cnt;
+      uint32_t* tail = cnt + BF_KMAX;
+      uint32_t* tend = tail + BF_NTS;
+      uint32_t* fill = tend + BF_NTS;
+      uint32_t* done = fill + BF_NTS;
+      int32_t* stage = reinterpret_cast<int32_t*>(done + BF_NTS);
+      {
+        constexpr int PER = (BF_KMAX + BN_NT - 1) / BN_NT;
+        uint32_t beg = 0, big = 0;
+        // positions relative to p0 are below the scratch size (< 2^31)
+        for (int k = 0; k < PER; k++) {
+          const int b = b0 + tid * PER + k;
+          if (b < b1) {
+            const uint32_t sr = (uint32_t)(off[b] - p0), er = (uint32_t)(off[b + 1] - p0);
+            const uint32_t pr = b == b0 ? 0u : (uint32_t)(off[b - 1] - p0);
+            if (er - sr > BF_GROUP) big |= 1u << k;
+            if (b == b0 || er - sr > BF_GROUP || sr / BF_GROUP != pr / BF_GROUP) beg |= 1u << k;
+          }
+        }
+        int64_t ntot;
+        int t = (int)block_excl_scan64<BN_NT>(__popc(beg), &ntot) - 1;
+        // every read of a neighbour's entry of off is done (the scan
+        // synchronised); each thread now rewrites only its own entries.
+        // head[t] takes the target's first position for now.
+        for (int k = 0; k < PER; k++) {
+          const int b = b0 + tid * PER + k;
+          if (b < b1) {
+            if ((beg >> k) & 1) {
+              t++;
+              head[t] = (uint32_t)(off[b] - p0) | (((big >> k) & 1u) << 31);
+            }
+            off[b] = t;
+          }
+        }
+        if (tid == 0) s_nt = (int)ntot;
+        __syncthreads();
+        // padded starts: each target's count rounded up to a multiple of 8
+        const int nt = (int)ntot;
+        const uint32_t span = (uint32_t)(off_end - p0);
+        uint32_t st[PER + 1], kinds = 0, psum = 0;
+        for (int k = 0; k <= PER; k++) {
+          const int tt = tid * PER + k;
+          st[k] = tt < nt ? head[tt] : span;
+          if (k < PER && (st[k] >> 31)) kinds |= 1u << k;
+          st[k] &= 0x7fffffffu;
+        }
+        for (int k = 0; k < PER; k++)
+          if (tid * PER + k < nt) psum += (st[k + 1] - st[k] + 7) & ~7u;
+        uint32_t ps = (uint32_t)block_excl_scan64<BN_NT>(psum, nullptr);
+        for (int k = 0; k < PER; k++) {
+          const int tt = tid * PER + k;
+          if (tt < nt) {
+            const uint32_t c = st[k + 1] - st[k];
+            head[tt] = ps | (((kinds >> k) & 1u) << 31);
+            if (tt < BF_NTS) {
+              tail[tt] = tend[tt] = ps + c;
+              fill[tt] = done[tt] = 0;
+            }
+            ps += (c + 7) & ~7u;
+          }
+        }
+      }
+      __syncthreads();
+      const int ntargets = uni(s_nt);
+      // ---- pass 2: scatter the range's endpoints by target (one step in
+      // flight: its stores, not its loads, bound this pass)
+      bin_walk<1>(A.ncol, D, pre, nl, q_lo, q_hi, s_lo, [&](int32_t x, bool valid) {
+        bool flush = false;
+        int t = 0;
         if (valid) {
           const int w = fbin_of(A, x);
-          if (w >= b0 && w < b1) bins[atomicAdd(&off[w], 1) - p0] = x;
+          if (w >= b0 && w < b1) {
+            t = off[w];
+            if (t < BF_NTS) {
+              const uint32_t slot = atomicAdd(&fill[t], 1u);
+              if (slot < BF_SB) {
+                stage[t * BF_SB + slot] = x;
+                flush = atomicAdd(&done[t], 1u) == BF_SB - 1;
+              } else {
+                bins[atomicSub(&tail[t], 1u) - 1] = x;
+              }
+            } else {
+              bins[atomicAdd(&head[t], 1u) & 0x7fffffffu] = x;
+            }
+          }
+        }
+        if (flush) {
+          // every slot of the buffer is written: two 16-byte loads, the
+          // counters reset, two aligned 16-byte stores
+          const int4* sv = reinterpret_cast<const int4*>(stage + t * BF_SB);
+          const int4 v0 = sv[0], v1 = sv[1];
+          const uint32_t at = atomicAdd(&head[t], (uint32_t)BF_SB) & 0x7fffffffu;
+          done[t] = 0;
+          fill[t] = 0;
+          int4* dst = reinterpret_cast<int4*>(bins + at);
+          dst[0] = v0;
+          dst[1] = v1;
         }
       });
-      if (tid == 0) reads += (unsigned long long)total;
+      reads += (unsigned long long)total;
       __syncthreads();
-      // ---- pass 3: groups of buckets, wave wid taking groups wid, wid + 8,
-      // ...; the next group's bounds and endpoints are fetched before the
-      // current one is counted
-      const int64_t span = (int64_t)off[b1 - 1] - p0;
-      const int ngroups = (int)((span + BF_GROUP - 1) / BF_GROUP);
-      // first scatter position of bucket b of the range (b in [b0, b1])
-      auto bstart = [&](int b) -> int64_t { return b == 0 ? 0 : (int64_t)off[b - 1]; };
+      // buffers still holding entries, then the target ends (bit 31: dense)
+      // move to off[b0 ..) and the regions are cleared
+      for (int t = tid; t < ntargets && t < BF_NTS; t += BN_NT) {
+        const uint32_t at = head[t] & 0x7fffffffu;
+        for (uint32_t k = 0; k < done[t]; k++) bins[at + k] = stage[t * BF_SB + k];
+      }
+      __syncthreads();
+      for (int t = tid; t < ntargets; t += BN_NT)
+        off[b0 + t] = (int32_t)((t < BF_NTS ? tend[t] : head[t] & 0x7fffffffu) |
+                                (head[t] & 0x80000000u));
+      __syncthreads();
+      for (int i = tid; i < BN_NW * BF_WORDS / 4; i += BN_NT) cnt4[i] = make_uint4(0, 0, 0, 0);
+      if (tid == 0) {
+        s_next = 0;
+        s_nbig = 0;
+      }
+      __syncthreads();
+      // ---- pass 3: targets taken one at a time by waves; the next one is
+      // taken and its first endpoints loaded before the current is counted
       uint64_t* tab = reinterpret_cast<uint64_t*>(mycnt);
-      constexpr int HPER = (2 * BF_GROUP + WAVE - 1) / WAVE;  // hash-part endpoints per lane
-      struct Grp {
-        int l;                 // last bucket (-1: nothing to count)
-        int64_t hs, he, le;    // hash part [hs, he); lone dense bucket [he, le)
+      constexpr int HPER = (2 * BF_GROUP + WAVE - 1) / WAVE;  // hash-target endpoints per lane
+      // target t occupies [tbeg(t), its end): ends are exact, starts padded
+      auto tbeg = [&](int t) -> int64_t {
+        return t == 0 ? 0 : (int64_t)(((uint32_t)off[b0 + t - 1] & 0x7fffffffu) + 7 & ~7u);
       };
-      auto fetch = [&](int g, Grp& G, int32_t (&xv)[HPER]) {
-        G.l = -1;
-        G.hs = G.he = G.le = 0;
-        if (g < ngroups) {
-          const int64_t glo = p0 + (int64_t)g * BF_GROUP, ghi = glo + BF_GROUP;
-          const int f = wave_first_ge(b0, b1, glo, bstart);
-          int l = wave_first_ge(b0, b1, ghi, bstart) - 1;
-          if (l > b1 - 1) l = b1 - 1;
-          if (f <= l) {
-            // buckets f .. l - 1 hold fewer than BF_GROUP endpoints; bucket l
-            // joins them unless it alone holds more
-            const int64_t hs = bstart(f), ls = bstart(l), le = off[l];
-            G.l = l;
-            G.hs = hs;
-            G.he = le - ls > BF_GROUP ? ls : le;
-            G.le = le;
-          }
+      auto grab = [&]() {
+        int g = 0;
+        if (lane == 0) g = atomicAdd(&s_next, 1);
+        return uni(__shfl(g, 0, WAVE));
+      };
+      struct Tgt {
+        int t;
+        bool dense;
+        int64_t s, e;
+      };
+      auto fetch = [&](int t, Tgt& T, int32_t (&xv)[HPER]) {
+        T.t = t;
+        T.dense = false;
+        T.s = T.e = 0;
+        if (t < ntargets) {
+          const uint32_t ev = (uint32_t)uni(off[b0 + t]);
+          T.s = uni64(tbeg(t));
+          T.e = ev & 0x7fffffffu;
+          T.dense = (ev >> 31) != 0;
         }
 #pragma unroll
         for (int k = 0; k < HPER; k++) {
-          const int64_t q = G.hs + lane + k * WAVE;
-          xv[k] = q < G.he ? bins[q - p0] : -1;
+          const int64_t q = T.s + lane + k * WAVE;
+          xv[k] = q < T.e ? bins[q] : -1;
         }
       };
-      Grp cur, nxt;
+      Tgt cur, nxt;
       int32_t xc[HPER], xn[HPER];
-      fetch(wid, nxt, xn);
-      for (int g = wid; g < ngroups; g += BN_NW) {
+      fetch(grab(), nxt, xn);
+      while (nxt.t < ntargets) {
         cur = nxt;
 #pragma unroll
         for (int k = 0; k < HPER; k++) xc[k] = xn[k];
-        fetch(g + BN_NW, nxt, xn);
-        if (cur.l < 0) continue;  // a large bucket spans the whole stretch
-        if (cur.he > cur.hs) {
-          uint64_t part = 0;
-#pragma unroll
-          for (int k = 0; k < HPER; k++)
-            if (xc[k] >= 0) part += bin_hash_inc(tab, xc[k], &A.scal->err);
-          acc += part;
-          if (lane == 0) wedges += (unsigned long long)(cur.he - cur.hs);
+        fetch(grab(), nxt, xn);
+        const int64_t n_e = cur.e - cur.s;
+        if (n_e == 0) continue;
+        if (!cur.dense) {
+          // a hash target: fewer than 2 * BF_GROUP endpoints, all loaded
+          acc += bin_hash_batch(tab, xc, &A.scal->err);
+          wedges += (unsigned long long)n_e;
           wave_sync();
           region_clear(mycnt);
           wave_sync();
+          continue;
         }
-        if (cur.le == cur.he) continue;
-        const int l = cur.l;
-        const int64_t ls = cur.he, le = cur.le;
-        if (le - ls > BF_BIG) {
+        const int l = fbin_of(A, __shfl(xc[0], 0, WAVE));
+        if (n_e > BF_BIG) {
           if (lane == 0) {
             const int k = atomicAdd(&s_nbig, 1);
-            if (k < BF_BIGLIST) bigl[k] = (int16_t)l;
+            if (k < BF_BIGLIST) bigl[k] = (int16_t)cur.t;
           }
           continue;
         }
         // ---- one dense bucket in this wave's region
         const int32_t wlo = l << BF_SHIFT;
         uint64_t part = 0;
-        int64_t q = ls + lane;
-        for (; q + 3 * WAVE < le; q += 4 * WAVE) {
+#pragma unroll
+        for (int k = 0; k < HPER; k++)
+          if (xc[k] >= 0) part += window_inc(A, mycnt, wlo, xc[k]);
+        int64_t q = cur.s + HPER * WAVE + lane;
+        for (; q + 3 * WAVE < cur.e; q += 4 * WAVE) {
           int32_t xv[4];
 #pragma unroll
-          for (int k = 0; k < 4; k++) xv[k] = bins[q + k * WAVE - p0];
+          for (int k = 0; k < 4; k++) xv[k] = bins[q + k * WAVE];
 #pragma unroll
           for (int k = 0; k < 4; k++) part += window_inc(A, mycnt, wlo, xv[k]);
         }
-        for (; q < le; q += WAVE) part += window_inc(A, mycnt, wlo, bins[q - p0]);
+        for (; q < cur.e; q += WAVE) part += window_inc(A, mycnt, wlo, bins[q]);
         acc += part;
-        if (lane == 0) wedges += (unsigned long long)(le - ls);
+        wedges += (unsigned long long)n_e;
         wave_sync();
         region_clear(mycnt);
         wave_sync();
       }
       __syncthreads();
-      // dense buckets too large for one wave: the whole block, one region
-      // (listed, or found by a scan of the range when the list overflowed)
-      const int nbig = s_nbig;
-      auto count_big = [&](int b) {
-        const int64_t bs = bstart(b), be = off[b];
-        const int32_t wlo = b << BF_SHIFT;
+      // dense targets too large for one wave: the whole block, one region
+      // (listed, or found by a scan of the targets when the list overflowed)
+      const int nbig = uni(s_nbig);
+      auto count_big = [&](int t) {
+        const int64_t bs = tbeg(t), be = off[b0 + t] & 0x7fffffff;
+        const int32_t wlo = fbin_of(A, bins[bs]) << BF_SHIFT;
         uint64_t part = 0;
-        for (int64_t q = bs + tid; q < be; q += BN_NT) part += window_inc(A, cnt, wlo, bins[q - p0]);
+        for (int64_t q = bs + tid; q < be; q += BN_NT) part += window_inc(A, cnt, wlo, bins[q]);
         acc += part;
-        if (tid == 0) wedges += (unsigned long long)(be - bs);
+        if (wid == 0) wedges += (unsigned long long)(be - bs);
         __syncthreads();
         for (int i = tid; i < BF_WORDS; i += BN_NT) cnt[i] = 0;
         __syncthreads();
@@ -1281,8 +1440,10 @@ __global__ __launch_bounds__(BN_NT, 4) void k_c4_bin(C4Args A) {
       if (nbig <= BF_BIGLIST) {
         for (int k = 0; k < nbig; k++) count_big(bigl[k]);
       } else {
-        for (int b = b0; b < b1; b++)
-          if (off[b] - bstart(b) > BF_BIG) count_big(b);
+        for (int t = 0; t < ntargets; t++) {
+          const uint32_t ev = (uint32_t)off[b0 + t];
+          if ((ev >> 31) && (int64_t)(ev & 0x7fffffffu) - tbeg(t) > BF_BIG) count_big(t);
+        }
       }
       b0 = b1;
       __syncthreads();
@@ -1290,11 +1451,12 @@ __global__ __launch_bounds__(BN_NT, 4) void k_c4_bin(C4Args A) {
   }
   block_add_u128<BN_NT>(&A.scal->acc[ACC_C4], acc);
   if (A.flags & M4_STATS) {
-    block_add_u64<BN_NT>(&A.scal->stat[ST_WEDGES], wedges);
-    block_add_u64<BN_NT>(&A.scal->kstat[A.slot][0], wedges);
-    block_add_u64<BN_NT>(&A.scal->kstat[A.slot][1], owners);
-    block_add_u64<BN_NT>(&A.scal->kstat[A.slot][2], segs);
-    block_add_u64<BN_NT>(&A.scal->kstat[A.slot][3], reads);
+    const unsigned long long wv = lane == 0 ? wedges : 0, b0v = tid == 0 ? 1 : 0;
+    block_add_u64<BN_NT>(&A.scal->stat[ST_WEDGES], wv);
+    block_add_u64<BN_NT>(&A.scal->kstat[A.slot][0], wv);
+    block_add_u64<BN_NT>(&A.scal->kstat[A.slot][1], owners * b0v);
+    block_add_u64<BN_NT>(&A.scal->kstat[A.slot][2], segs * b0v);
+    block_add_u64<BN_NT>(&A.scal->kstat[A.slot][3], reads * b0v);
   }
 }
 
@@ -1304,7 +1466,7 @@ inline unsigned blocks_for(int64_t n, int nt) { return (unsigned)ceil_div(n > 0 
 
 Launch c4_plan(const Prep& P, const Classes& C, Scal* scal, const Tuning& tu, uint32_t flags,
                Arena& tmp, hipStream_t s, int num_cu, KTimer* kt,
-               const std::function<char*(size_t)>& big_scratch) {
+               const std::function<char*(size_t)>& big_scratch, bool* binned) {
   const int64_t n = P.n;
   if (n == 0 || P.m == 0) return [](hipStream_t) {};
   int64_t* wub = tmp.take<int64_t>(n);
@@ -1350,6 +1512,7 @@ Launch c4_plan(const Prep& P, const Classes& C, Scal* scal, const Tuning& tu, ui
   // segment descriptors serves both
   const int64_t H = hstart[CB_BIN + 1] - hstart[CB_WIN];
   const int64_t HB = hstart[CB_BIN + 1] - hstart[CB_BIN];
+  if (binned) *binned = HB > 0;
   int4* desc = nullptr;
   int64_t* seg_pre = nullptr;
   int32_t* seg_cnt = nullptr;
@@ -1372,9 +1535,9 @@ Launch c4_plan(const Prep& P, const Classes& C, Scal* scal, const Tuning& tu, ui
     size_t bb = 0;
     if (HB > 0) {
       const int64_t cap = tu.c4_bin_cap > 0 ? tu.c4_bin_cap : int64_t(1) << 20;
-      bin_cap = std::min<int64_t>(cap, std::max<int64_t>(P.nnz, 1));
+      bin_cap = (std::min<int64_t>(cap, std::max<int64_t>(P.nnz, 1)) + 7) & ~int64_t(7);
       bin_grid = (unsigned)std::min<int64_t>(2 * (int64_t)num_cu, HB);
-      bb = (size_t)bin_grid * (size_t)bin_cap * 4;
+      bb = (size_t)bin_grid * (size_t)(bin_cap + 8 * BF_KMAX) * 4;
     }
     char* scr = big_scratch(db + cb + pb + bb);
     if (!scr) throw Fail(M4_ENOMEM, "no room for 4-cycle segment descriptors");

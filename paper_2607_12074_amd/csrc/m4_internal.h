@@ -224,10 +224,11 @@ inline void tri_run(const Prep& P, Scal* scal, const Tuning& tu, uint32_t flags,
   tri_plan(P, scal, tu, flags, cache_rows, tmp, s, num_cu, big_scratch, kt)(s);
 }
 
-// m4_c4.hip
+// m4_c4.hip (binned, if given, is set when owners go to the binning kernel,
+// which holds every CU with persistent workgroups and all of their LDS)
 Launch c4_plan(const Prep& P, const Classes& C, Scal* scal, const Tuning& tu, uint32_t flags,
                Arena& tmp, hipStream_t s, int num_cu, KTimer* kt,
-               const std::function<char*(size_t)>& big_scratch);
+               const std::function<char*(size_t)>& big_scratch, bool* binned = nullptr);
 inline void c4_run(const Prep& P, const Classes& C, Scal* scal, const Tuning& tu, uint32_t flags,
                    Arena& tmp, hipStream_t s, int num_cu, KTimer* kt,
                    const std::function<char*(size_t)>& big_scratch) {

@@ -19,7 +19,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <thread>
 #include <vector>
 
 #include "m4_ctx.h"
@@ -66,6 +68,29 @@ struct HostCsr {
   Pinned ncol;  // int32[nnz]
   const int32_t* col() const { return reinterpret_cast<const int32_t*>(ncol.p); }
 };
+
+// Host threads for the halo planning and gathers (at most 16).
+int host_threads() {
+  const unsigned h = std::thread::hardware_concurrency();
+  return (int)std::max(1u, std::min(16u, h));
+}
+
+// f(begin, end) over [0, n) split evenly across nt threads (the caller's
+// thread takes the first share); f must not throw.
+template <class F>
+void parallel_for(int64_t n, int nt, F&& f) {
+  if (n <= 0) return;
+  nt = (int)std::min<int64_t>(nt, n);
+  if (nt <= 1) {
+    f(int64_t(0), n);
+    return;
+  }
+  std::vector<std::thread> th;
+  th.reserve(nt - 1);
+  for (int t = 1; t < nt; t++) th.emplace_back([&, t] { f(n * t / nt, n * (t + 1) / nt); });
+  f(int64_t(0), n / nt);
+  for (auto& x : th) x.join();
+}
 
 double now_ms() {
   return std::chrono::duration<double, std::milli>(
@@ -254,13 +279,20 @@ int count_partitioned(m4_ctx* c, const m4_csr* g, const m4_opts* o, uint64_t out
       hrp2[0] = 0;
       for (int64_t i = 0; i < R; i++) {
         const int32_t v = H.perm[r0 + i];
-        const int64_t d = rp[v + 1] - rp[v];
-        memcpy(hcc + hrp2[i], col + rp[v], d * 4);
-        hrp2[i + 1] = hrp2[i] + d;
-        hperm[i] = (int32_t)i;
-        hnptr[i] = hrp2[i];
-        hdr[i] = (int32_t)d;
+        hrp2[i + 1] = hrp2[i] + (rp[v + 1] - rp[v]);
       }
+      const double tg = now_ms();
+      parallel_for(R, host_threads(), [&](int64_t a, int64_t b) {
+        for (int64_t i = a; i < b; i++) {
+          const int32_t v = H.perm[r0 + i];
+          const int64_t d = hrp2[i + 1] - hrp2[i];
+          memcpy(hcc + hrp2[i], col + rp[v], d * 4);
+          hperm[i] = (int32_t)i;
+          hnptr[i] = hrp2[i];
+          hdr[i] = (int32_t)d;
+        }
+      });
+      t_host += now_ms() - tg;
       hnptr[R] = hrp2[R];
       up(crp, hrp2, (R + 1) * 8);
       up(cperm, hperm, R * 4);
@@ -317,6 +349,7 @@ int count_partitioned(m4_ctx* c, const m4_csr* g, const m4_opts* o, uint64_t out
   };
   std::vector<uint32_t> mark(n, 0);
   uint32_t stamp = 0;
+  const int nthreads = host_threads();
   const int32_t* hc = H.col();
 
   // Uploads rows of a partition: (row, first stored entry, count) triples.
@@ -341,16 +374,23 @@ int count_partitioned(m4_ctx* c, const m4_csr* g, const m4_opts* o, uint64_t out
     int32_t* hl = reinterpret_cast<int32_t*>(S.p + al((2 * rows.size() + 2) * 8));
     int32_t* hcc = reinterpret_cast<int32_t*>(S.p + al((2 * rows.size() + 2) * 8) +
                                               al((rows.size() + 1) * 4));
-    int64_t off = 0;
     const double tg = now_ms();
+    // row offsets in the buffer, then the copies on all host threads
+    int64_t off = 0;
     for (size_t i = 0; i < rows.size(); i++) {
-      const RowPart& r = rows[i];
-      memcpy(hcc + off, hc + H.nptr[r.v] + r.first, (size_t)r.len * 4);
-      hp[2 * i] = r.v;
-      hp[2 * i + 1] = off - r.first;  // so that nptr[v] + index-in-row addresses the buffer
-      hl[i] = r.first + r.len;        // stored prefix length (when the row starts at 0)
-      off += r.len;
+      hp[2 * i + 1] = off;
+      off += rows[i].len;
     }
+    parallel_for((int64_t)rows.size(), nthreads, [&](int64_t a, int64_t b) {
+      for (int64_t i = a; i < b; i++) {
+        const RowPart& r = rows[i];
+        const int64_t o = hp[2 * i + 1];
+        memcpy(hcc + o, hc + H.nptr[r.v] + r.first, (size_t)r.len * 4);
+        hp[2 * i] = r.v;
+        hp[2 * i + 1] = o - r.first;  // so that nptr[v] + index-in-row addresses the buffer
+        hl[i] = (int32_t)(r.first + r.len);  // stored prefix length (when the row starts at 0)
+      }
+    });
     t_host += now_ms() - tg;
     up(dpairs, hp, rows.size() * 16);
     up(dlens, hl, rows.size() * 4);
@@ -391,7 +431,16 @@ int count_partitioned(m4_ctx* c, const m4_csr* g, const m4_opts* o, uint64_t out
         // owner hi with its out-list and the out-lists of its out-neighbours
         size_t add = need_row((int32_t)hi);
         const int64_t b0 = H.nptr[hi] + H.dlo[hi];
-        for (int64_t j = 0; j < H.dplus[hi]; j++) add += need_row(hc[b0 + j]);
+        constexpr int kAhead = 16;  // mark[] and the degree arrays miss the caches
+        for (int64_t j = 0; j < H.dplus[hi]; j++) {
+          if (j + kAhead < H.dplus[hi]) {
+            const int32_t w = hc[b0 + j + kAhead];
+            __builtin_prefetch(&mark[w]);
+            __builtin_prefetch(&H.dplus[w]);
+            __builtin_prefetch(&H.dlo[w]);
+          }
+          add += need_row(hc[b0 + j]);
+        }
         if (bytes + add > cap_rows && hi > lo) break;
         bytes += add;
         auto put = [&](int32_t v) {
@@ -420,52 +469,96 @@ int count_partitioned(m4_ctx* c, const m4_csr* g, const m4_opts* o, uint64_t out
   // ---- 4. 4-cycle anchor over owner ranges with lower halos cut below hi
   {
     const size_t cap_rows = D.cap > fixed_used + c4_tmp ? D.cap - fixed_used - c4_tmp : 0;
-    std::vector<int32_t> stored(n, 0);
+    // for every lower neighbour v of an owner u, the entries of row v up to
+    // and including u: u sits at position j of row v's upper part, and v's
+    // slot in u's lower part is the count of lower neighbours of u below v,
+    // so one ascending sweep over the rows fills every slot.  Each host thread
+    // sweeps all rows for the owners of its own share (balanced by lower
+    // entries), keeping per-owner cursors.
+    const double tq = now_ms();
+    std::vector<int64_t> lptr(n + 1, 0);
+    for (int64_t u = 0; u < n; u++) lptr[u + 1] = lptr[u] + (u >= C.r1 ? H.dlo[u] : 0);
+    std::vector<int32_t> ulen((size_t)lptr[n] + 1);
+    {
+      std::vector<int64_t> cut(nthreads + 1, n);
+      cut[0] = C.r1;
+      for (int t = 1; t < nthreads; t++)
+        cut[t] = std::lower_bound(lptr.begin(), lptr.end(), lptr[n] * t / nthreads) - lptr.begin();
+      for (int t = 1; t <= nthreads; t++) cut[t] = std::max(cut[t], cut[t - 1]);
+      parallel_for(nthreads, nthreads, [&](int64_t a, int64_t b) {
+        for (int64_t t = a; t < b; t++) {
+          const int64_t ua = cut[t], ube = cut[t + 1];
+          if (ua >= ube) continue;
+          std::vector<int32_t> cur(ube - ua, 0);
+          // rows below ua cannot hold an owner of this share in their upper part
+          for (int64_t v = 0; v < ube; v++) {
+            const int32_t* rb = hc + H.nptr[v];
+            int32_t j = H.dlo[v];
+            const int32_t e = H.dr[v];
+            if (e - j > 16) j = (int32_t)(std::lower_bound(rb + j, rb + e, (int32_t)ua) - rb);
+            for (; j < e; j++) {
+              const int32_t u = rb[j];
+              if (u >= ube) break;
+              if (u < ua) continue;
+              ulen[lptr[u] + cur[u - ua]++] = j + 1;
+            }
+          }
+        }
+      });
+    }
+    t_host += now_ms() - tq;
+    // per vertex: the range that holds its row (stamp) and the stored length
+    struct Held {
+      uint32_t stamp;
+      int32_t len;
+    };
+    std::vector<Held> held(n, Held{0, 0});
+    uint32_t rstamp = 0;
     int64_t lo = C.r1;
     // owners below r1 have degree <= 1 and no 4-cycle
     while (lo < n) {
-      stamp++;
+      rstamp++;
       rows.clear();
       std::vector<int32_t> members;
       // alignment of the descriptor arrays in the scratch region
       size_t bytes = 512;
       int64_t hi = lo;
-      uint64_t segs = 0;
       const double tp = now_ms();
       while (hi < n) {
         const int64_t u = hi;
-        // rows already held gain the entry u when the upper end moves past u
-        size_t add = 0;
-        const int64_t ub = H.nptr[u], ue = H.nptr[u + 1];
-        for (int64_t p = ub; p < ue; p++)
-          if (mark[hc[p]] == stamp) add += 4;
-        std::vector<std::pair<int32_t, int32_t>> fresh;
-        if (mark[u] != stamp) fresh.push_back({(int32_t)u, H.dlo[u]});
-        for (int64_t p = ub; p < ub + H.dlo[u]; p++) {
-          const int32_t v = hc[p];
-          if (mark[v] == stamp) continue;
-          // row v up to and including u
-          const int32_t* rb = hc + H.nptr[v];
-          const int64_t len = std::upper_bound(rb, rb + H.dr[v], (int32_t)u) - rb;
-          fresh.push_back({v, (int32_t)len});
+        const int64_t ub = H.nptr[u];
+        const int32_t dl = H.dlo[u];
+        const int32_t* lu = ulen.data() + lptr[u];
+        // a held row v in L(u) gains the entry u when the upper end moves past
+        // u; a new one is stored up to and including u; u's own lower part
+        // joins (its later entries come as the end moves on)
+        size_t add = (size_t)dl * 4 + 32 + (size_t)dl * 16 + 4;
+        constexpr int kAhead = 16;  // held[] is far larger than the caches
+        for (int32_t j = 0; j < dl; j++) {
+          if (j + kAhead < dl) __builtin_prefetch(&held[hc[ub + j + kAhead]]);
+          const Held& h = held[hc[ub + j]];
+          add += h.stamp == rstamp ? 4 : (size_t)lu[j] * 4 + 32;
         }
-        for (auto& f : fresh) add += (size_t)f.second * 4 + 32;
-        add += (size_t)H.dlo[u] * 16 + 4;  // segment descriptors and their count
         if (bytes + add > cap_rows && hi > lo) break;
         bytes += add;
-        for (int64_t p = ub; p < ue; p++)
-          if (mark[hc[p]] == stamp) stored[hc[p]]++;
-        for (auto& f : fresh) {
-          mark[f.first] = stamp;
-          stored[f.first] = f.second;
-          members.push_back(f.first);
+        for (int32_t j = 0; j < dl; j++) {
+          const int32_t v = hc[ub + j];
+          Held& h = held[v];
+          if (h.stamp == rstamp) {
+            h.len++;
+          } else {
+            h.stamp = rstamp;
+            h.len = lu[j];
+            members.push_back(v);
+          }
         }
-        segs += H.dlo[u];
+        held[u] = Held{rstamp, dl};
+        members.push_back((int32_t)u);
         hi++;
       }
       t_host += now_ms() - tp;
       if (bytes > cap_rows) throw Fail(M4_ENOMEM, "device budget below one owner's halo");
-      for (int32_t v : members) rows.push_back({v, 0, stored[v]});
+      for (int32_t v : members) rows.push_back({v, 0, held[v].len});
       P.ncol = upload_rows(true, 0);
       P.row_len = rowlen;
       P.own_lo = lo;
