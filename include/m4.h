@@ -257,6 +257,28 @@ typedef struct m4_batch_s {
 int m4_count_batch(m4_ctx* ctx, const m4_batch* b, const m4_opts* opts,
                    uint64_t* out, m4_stats* st);
 
+/* ------------------------------------------------ partition planning ----
+ * The host planner of the halo-partitioned path (Section III-E), exposed so
+ * that its ranges can be checked without a GPU.  Input: a rank-space CSR in
+ * host memory (rows sorted, ranks in (degree, id) order, dlo[v] entries of
+ * row v below v and dplus[v] above it).  kind 0 plans triangle / 4-clique
+ * owner ranges over [0, n) (a range holds its owners' out-lists and their
+ * out-neighbours' out-lists); kind 1 plans 4-cycle owner ranges over
+ * [r1, n) (a range holds the rows of its owners and of their lower
+ * neighbours, each cut below the range's end).  Every range but a lone owner
+ * fits cap_bytes by the path's own accounting.  Output, caller-owned: range k
+ * ends at range_end[k] (starting where range k-1 ended) and owns rows
+ * [range_rows[k-1], range_rows[k]) of rows_v / rows_first / rows_len (entries
+ * [first, first + len) of row v); *nranges = ranges written.  Returns
+ * M4_ENOMEM when one owner alone exceeds cap_bytes (the ranges before it are
+ * written), M4_ERANGE when max_ranges or max_rows is too small, M4_EINVAL on
+ * bad arguments.  Host only; no device is touched. */
+int m4_plan_partitions(int kind, int64_t n, const int64_t* nptr, const int32_t* col,
+                       const int32_t* dlo, const int32_t* dplus, int64_t r1,
+                       uint64_t cap_bytes, int64_t max_ranges, int64_t max_rows,
+                       int64_t* range_end, int64_t* range_rows, int32_t* rows_v,
+                       int64_t* rows_first, int32_t* rows_len, int64_t* nranges);
+
 /* -------------------------------------------------------------- serving --
  * A request loop with continuous batching: submitted graphs are copied into
  * pinned staging, admitted to the device while their CSR and work arrays fit
@@ -279,7 +301,8 @@ int m4_server_drain(m4_server* s);
 void m4_server_destroy(m4_server* s);
 /* Milliseconds on the server clock (the clock of m4_result times). */
 double m4_server_now_ms(const m4_server* s);
-/* Largest device footprint admitted at once (never above the budget), number
+/* Largest device memory the server held at once (lane arenas, the worker's
+ * workspaces and the running work's reserve; never above the budget), number
  * of fused launches and completed requests so far. */
 int m4_server_stats(const m4_server* s, uint64_t* max_inflight_bytes, uint64_t* launches,
                     uint64_t* completed);

@@ -139,6 +139,8 @@ def lib():
         L.m4_server_destroy.restype = None
         L.m4_server_now_ms.argtypes = [p]
         L.m4_server_now_ms.restype = ctypes.c_double
+        L.m4_plan_partitions.argtypes = [i, ctypes.c_int64, p, p, p, p, ctypes.c_int64, u64,
+                                         ctypes.c_int64, ctypes.c_int64, p, p, p, p, p, p]
         _lib = L
     return _lib
 
@@ -348,6 +350,37 @@ class Context:
 
 
 _default = None
+
+
+def plan_partitions(kind, nptr, col, dlo, dplus, r1, cap_bytes, max_ranges=None,
+                    max_rows=None):
+    """Owner ranges of the host partition planner (``m4_plan_partitions``) on
+    a rank-space CSR in host memory: kind 0 triangle ranges, 1 4-cycle
+    ranges.  Returns (status, ends, rows) with rows[k] a list of (v, first,
+    len) for range k."""
+    n = len(nptr) - 1
+    nptr = np.ascontiguousarray(nptr, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    dlo = np.ascontiguousarray(dlo, dtype=np.int32)
+    dplus = np.ascontiguousarray(dplus, dtype=np.int32)
+    mr = max_ranges if max_ranges is not None else n + 1
+    mw = max_rows if max_rows is not None else (n + 1) * (n + 1)
+    ends = np.zeros(max(mr, 1), np.int64)
+    rr = np.zeros(max(mr, 1), np.int64)
+    rv = np.zeros(max(mw, 1), np.int32)
+    rf = np.zeros(max(mw, 1), np.int64)
+    rl = np.zeros(max(mw, 1), np.int32)
+    k = ctypes.c_int64(0)
+    ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    rc = lib().m4_plan_partitions(int(kind), n, ptr(nptr), ptr(col), ptr(dlo), ptr(dplus),
+                                  int(r1), int(cap_bytes), mr, mw, ptr(ends), ptr(rr), ptr(rv),
+                                  ptr(rf), ptr(rl), ctypes.byref(k))
+    rows, b = [], 0
+    for j in range(k.value):
+        e = int(rr[j])
+        rows.append(list(zip(rv[b:e].tolist(), rf[b:e].tolist(), rl[b:e].tolist())))
+        b = e
+    return rc, ends[:k.value].tolist(), rows
 
 
 def default_context() -> Context:

@@ -254,6 +254,9 @@ Tuning tuning_for(const m4_ctx* c, const m4_opts* o) {
   // C4_MED_SLOTS keys at load <= 3/4 in one pass
   tu.c4_light_max = std::max(0, std::min(tu.c4_light_max, C4_HASH_SLOTS / 2));
   tu.c4_med_max = std::max(0, std::min(tu.c4_med_max, 3 * C4_MED_SLOTS / 4));
+  // the binned 4-cycle owners take scratch sized by the CU count, which a
+  // device budget does not provide for
+  if (o && o->device_budget_bytes > 0) tu.c4_bin_win = 0;
   return tu;
 }
 

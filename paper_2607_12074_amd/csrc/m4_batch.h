@@ -49,6 +49,14 @@ struct BatchPlan {
   BatchArgs args{};
 };
 
+// Device layout of one fused launch over G graphs (staged: the packed arena
+// is copied in from pinned host memory); need is the device bytes it takes.
+struct BatchLayout {
+  size_t o_perm, o_dr, o_dlo, o_dplus, o_nptr, o_optr, o_ncol, o_t, o_order, o_out, o_status,
+      o_work, o_arena, arena_bytes, need;
+};
+BatchLayout batch_layout(int64_t G, int64_t sum_n, int64_t sum_nnz, bool staged);
+
 int batch_variant_kb(int variant);
 // true when graph (n, rp) is counted by the fused kernel rather than by the
 // single-graph path (the kernel applies the same test to the arena itself)

@@ -481,6 +481,32 @@ bool batch_graph_fits(int64_t n, const int64_t* rp, int variant) {
 // launch.
 // dev_arena: device pointers of the arena, or null to stage the host arena
 // into pinned memory and upload it within the launch.
+BatchLayout batch_layout(int64_t G, int64_t sum_n, int64_t sum_nnz, bool staged) {
+  BatchLayout L{};
+  size_t need = 0;
+  auto add = [&](size_t bytes) {
+    size_t o2 = need;
+    need += al(bytes + 8);
+    return o2;
+  };
+  L.o_perm = add(sum_n * 4);
+  L.o_dr = add(sum_n * 4);
+  L.o_dlo = add(sum_n * 4);
+  L.o_dplus = add(sum_n * 4);
+  L.o_nptr = add((sum_n + G) * 8);
+  L.o_optr = add((sum_n + G) * 8);
+  L.o_ncol = add(sum_nnz * 4);
+  L.o_t = add(sum_nnz / 2 * 4);
+  L.o_order = add(G * 4);
+  L.o_out = add(G * 48);
+  L.o_status = add(G * 4);
+  L.o_work = add(64);
+  L.arena_bytes = (size_t)(G + 1) * 16 + (sum_n + G) * 8 + sum_nnz * 4;
+  if (staged) L.o_arena = add(L.arena_bytes);
+  L.need = need;
+  return L;
+}
+
 void batch_prepare(m4_ctx* c, BatchBuffers& B, BatchPlan& P, int64_t G, const int64_t* hvoff,
                    const int64_t* heoff, const m4_batch* dev_arena, int variant, int light,
                    uint32_t flags, uint32_t cache_rows, hipStream_t s) {
@@ -504,21 +530,15 @@ void batch_prepare(m4_ctx* c, BatchBuffers& B, BatchPlan& P, int64_t G, const in
   if ((int64_t)grid > (int64_t)P.order.size()) grid = (int)std::max<size_t>(1, P.order.size());
   P.grid = grid;
 
-  size_t need = 0;
-  auto add = [&](size_t bytes) {
-    size_t o2 = need;
-    need += al(bytes + 8);
-    return o2;
-  };
-  const size_t o_perm = add(sum_n * 4), o_dr = add(sum_n * 4), o_dlo = add(sum_n * 4),
-               o_dplus = add(sum_n * 4), o_nptr = add((sum_n + G) * 8),
-               o_optr = add((sum_n + G) * 8), o_ncol = add(sum_nnz * 4),
-               o_t = add(sum_nnz / 2 * 4), o_order = add(G * 4), o_out = add(G * 48),
-               o_status = add(G * 4), o_work = add(64);
-  P.arena_bytes = (size_t)(G + 1) * 16 + (sum_n + G) * 8 + sum_nnz * 4;
   P.staged = dev_arena == nullptr;
-  if (P.staged) P.o_arena = add(P.arena_bytes);
-  B.dev.ensure(need, s);
+  const BatchLayout Lo = batch_layout(G, sum_n, sum_nnz, P.staged);
+  const size_t o_perm = Lo.o_perm, o_dr = Lo.o_dr, o_dlo = Lo.o_dlo, o_dplus = Lo.o_dplus,
+               o_nptr = Lo.o_nptr, o_optr = Lo.o_optr, o_ncol = Lo.o_ncol, o_t = Lo.o_t,
+               o_order = Lo.o_order, o_out = Lo.o_out, o_status = Lo.o_status,
+               o_work = Lo.o_work;
+  P.arena_bytes = Lo.arena_bytes;
+  if (P.staged) P.o_arena = Lo.o_arena;
+  B.dev.ensure(Lo.need, s);
   char* d = B.dev.ptr;
   if (B.h_out_cap < (size_t)G) {
     if (B.h_out) (void)hipHostFree(B.h_out);

@@ -98,6 +98,165 @@ double now_ms() {
       .count();
 }
 
+// A row of a partition: entries [first, first + len) of row v.
+struct RowPart {
+  int32_t v;
+  int64_t first;
+  int32_t len;
+};
+
+// Rank-space rows in host memory, as the range planners read them.
+struct HostRows {
+  int64_t n = 0;
+  const int64_t* nptr = nullptr;
+  const int32_t* col = nullptr;
+  const int32_t* dr = nullptr;
+  const int32_t* dlo = nullptr;
+  const int32_t* dplus = nullptr;
+};
+
+// Owner ranges of the triangle / 4-clique anchor (owner = lowest vertex):
+// a range holds its owners' out-lists and the out-lists of their
+// out-neighbours (radius-1 oriented halo), 4 bytes per entry and 28 per row.
+struct TriPlanner {
+  const HostRows& H;
+  std::vector<uint32_t> mark;
+  uint32_t stamp = 0;
+  explicit TriPlanner(const HostRows& h) : H(h), mark(h.n, 0) {}
+  // the largest range [lo, hi) whose rows fit cap bytes (at least one owner;
+  // bytes then tells whether even that one fits)
+  int64_t next(int64_t lo, size_t cap, std::vector<RowPart>& rows, size_t& bytes) {
+    stamp++;
+    rows.clear();
+    bytes = 0;
+    int64_t hi = lo;
+    auto need_row = [&](int32_t v) {
+      return mark[v] == stamp ? (size_t)0 : (size_t)H.dplus[v] * 4 + 28;
+    };
+    auto put = [&](int32_t v) {
+      if (mark[v] == stamp) return;
+      mark[v] = stamp;
+      rows.push_back({v, (int64_t)H.dlo[v], H.dplus[v]});
+    };
+    while (hi < H.n) {
+      size_t add = need_row((int32_t)hi);
+      const int64_t b0 = H.nptr[hi] + H.dlo[hi];
+      const int32_t dp = H.dplus[hi];
+      constexpr int kAhead = 16;  // mark[] and the degree arrays miss the caches
+      for (int32_t j = 0; j < dp; j++) {
+        if (j + kAhead < dp) {
+          const int32_t w = H.col[b0 + j + kAhead];
+          __builtin_prefetch(&mark[w]);
+          __builtin_prefetch(&H.dplus[w]);
+          __builtin_prefetch(&H.dlo[w]);
+        }
+        add += need_row(H.col[b0 + j]);
+      }
+      if (bytes + add > cap && hi > lo) break;
+      bytes += add;
+      put((int32_t)hi);
+      for (int32_t j = 0; j < dp; j++) put(H.col[b0 + j]);
+      hi++;
+    }
+    return hi;
+  }
+};
+
+// Owner ranges of the 4-cycle anchor (owner = highest vertex, from r1): a
+// range holds the rows of its owners and of their lower neighbours, each cut
+// below the range's end: 4 bytes per entry, 32 per row, 16 per lower
+// neighbour of an owner (segment descriptor) and 4 per owner, plus 512 of
+// alignment.
+struct C4Planner {
+  const HostRows& H;
+  int64_t r1;
+  std::vector<int64_t> lptr;
+  std::vector<int32_t> ulen;  // per lower entry of an owner: row v's entries up to the owner
+  struct Held {
+    uint32_t stamp;
+    int32_t len;
+  };
+  std::vector<Held> held;
+  uint32_t stamp = 0;
+  // For every lower neighbour v of an owner u, u sits at position j of row
+  // v's upper part, and v's slot in u's lower part is the count of lower
+  // neighbours of u below v, so one ascending sweep over the rows fills
+  // every slot.  Each host thread sweeps all rows for the owners of its own
+  // share (balanced by lower entries), keeping per-owner cursors.
+  C4Planner(const HostRows& h, int64_t r1_, int nthreads)
+      : H(h), r1(r1_), lptr(h.n + 1, 0), held(h.n, Held{0, 0}) {
+    const int64_t n = H.n;
+    for (int64_t u = 0; u < n; u++) lptr[u + 1] = lptr[u] + (u >= r1 ? H.dlo[u] : 0);
+    ulen.assign((size_t)lptr[n] + 1, 0);
+    std::vector<int64_t> cut(nthreads + 1, n);
+    cut[0] = std::min(r1, n);
+    for (int t = 1; t < nthreads; t++)
+      cut[t] = std::lower_bound(lptr.begin(), lptr.end(), lptr[n] * t / nthreads) - lptr.begin();
+    for (int t = 1; t <= nthreads; t++) cut[t] = std::max(cut[t], cut[t - 1]);
+    parallel_for(nthreads, nthreads, [&](int64_t a, int64_t b) {
+      for (int64_t t = a; t < b; t++) {
+        const int64_t ua = cut[t], ube = cut[t + 1];
+        if (ua >= ube) continue;
+        std::vector<int32_t> cur(ube - ua, 0);
+        // rows from ube on cannot hold an owner of this share in their upper part
+        for (int64_t v = 0; v < ube; v++) {
+          const int32_t* rb = H.col + H.nptr[v];
+          int32_t j = H.dlo[v];
+          const int32_t e = H.dr[v];
+          if (e - j > 16) j = (int32_t)(std::lower_bound(rb + j, rb + e, (int32_t)ua) - rb);
+          for (; j < e; j++) {
+            const int32_t u = rb[j];
+            if (u >= ube) break;
+            if (u < ua) continue;
+            ulen[lptr[u] + cur[u - ua]++] = j + 1;
+          }
+        }
+      }
+    });
+  }
+  int64_t next(int64_t lo, size_t cap, std::vector<RowPart>& rows, size_t& bytes) {
+    stamp++;
+    rows.clear();
+    std::vector<int32_t> members;
+    bytes = 512;
+    int64_t hi = lo;
+    while (hi < H.n) {
+      const int64_t u = hi;
+      const int64_t ub = H.nptr[u];
+      const int32_t dl = H.dlo[u];
+      const int32_t* lu = ulen.data() + lptr[u];
+      // a held row v in L(u) gains the entry u when the end moves past u; a
+      // new one is stored up to and including u; u's own lower part joins
+      // (its later entries come as the end moves on)
+      size_t add = (size_t)dl * 4 + 32 + (size_t)dl * 16 + 4;
+      constexpr int kAhead = 16;  // held[] is far larger than the caches
+      for (int32_t j = 0; j < dl; j++) {
+        if (j + kAhead < dl) __builtin_prefetch(&held[H.col[ub + j + kAhead]]);
+        const Held& h = held[H.col[ub + j]];
+        add += h.stamp == stamp ? 4 : (size_t)lu[j] * 4 + 32;
+      }
+      if (bytes + add > cap && hi > lo) break;
+      bytes += add;
+      for (int32_t j = 0; j < dl; j++) {
+        const int32_t v = H.col[ub + j];
+        Held& h = held[v];
+        if (h.stamp == stamp) {
+          h.len++;
+        } else {
+          h.stamp = stamp;
+          h.len = lu[j];
+          members.push_back(v);
+        }
+      }
+      held[u] = Held{stamp, dl};
+      members.push_back((int32_t)u);
+      hi++;
+    }
+    for (int32_t v : members) rows.push_back({v, 0, held[v].len});
+    return hi;
+  }
+};
+
 }  // namespace
 
 struct PartState {
@@ -347,18 +506,18 @@ int count_partitioned(m4_ctx* c, const m4_csr* g, const m4_opts* o, uint64_t out
     if (scratch_floor + b > D.cap) return nullptr;
     return D.base + (D.cap - b);
   };
-  std::vector<uint32_t> mark(n, 0);
-  uint32_t stamp = 0;
   const int nthreads = host_threads();
   const int32_t* hc = H.col();
 
   // Uploads rows of a partition: (row, first stored entry, count) triples.
-  struct RowPart {
-    int32_t v;
-    int64_t first;
-    int32_t len;
-  };
   std::vector<RowPart> rows;
+  HostRows HR;
+  HR.n = n;
+  HR.nptr = H.nptr.data();
+  HR.col = hc;
+  HR.dr = H.dr.data();
+  HR.dlo = H.dlo.data();
+  HR.dplus = H.dplus.data();
   auto upload_rows = [&](bool with_len, int64_t nptr_bias_dlo) -> int32_t* {
     (void)nptr_bias_dlo;
     int64_t ent = 0;
@@ -416,42 +575,12 @@ int count_partitioned(m4_ctx* c, const m4_csr* g, const m4_opts* o, uint64_t out
   // ---- 3. triangle / 4-clique anchors over owner ranges with oriented halos
   {
     const size_t cap_rows = D.cap > fixed_used + tri_tmp ? D.cap - fixed_used - tri_tmp : 0;
+    TriPlanner plan(HR);
     int64_t lo = 0;
     while (lo < n) {
-      stamp++;
-      rows.clear();
-      size_t bytes = 0;
-      int64_t hi = lo;
-      auto need_row = [&](int32_t v) {
-        if (mark[v] == stamp) return (size_t)0;
-        return (size_t)H.dplus[v] * 4 + 28;
-      };
       const double tp = now_ms();
-      while (hi < n) {
-        // owner hi with its out-list and the out-lists of its out-neighbours
-        size_t add = need_row((int32_t)hi);
-        const int64_t b0 = H.nptr[hi] + H.dlo[hi];
-        constexpr int kAhead = 16;  // mark[] and the degree arrays miss the caches
-        for (int64_t j = 0; j < H.dplus[hi]; j++) {
-          if (j + kAhead < H.dplus[hi]) {
-            const int32_t w = hc[b0 + j + kAhead];
-            __builtin_prefetch(&mark[w]);
-            __builtin_prefetch(&H.dplus[w]);
-            __builtin_prefetch(&H.dlo[w]);
-          }
-          add += need_row(hc[b0 + j]);
-        }
-        if (bytes + add > cap_rows && hi > lo) break;
-        bytes += add;
-        auto put = [&](int32_t v) {
-          if (mark[v] == stamp) return;
-          mark[v] = stamp;
-          rows.push_back({v, (int64_t)H.dlo[v], H.dplus[v]});
-        };
-        put((int32_t)hi);
-        for (int64_t j = 0; j < H.dplus[hi]; j++) put(hc[b0 + j]);
-        hi++;
-      }
+      size_t bytes = 0;
+      const int64_t hi = plan.next(lo, cap_rows, rows, bytes);
       t_host += now_ms() - tp;
       if (bytes > cap_rows) throw Fail(M4_ENOMEM, "device budget below one owner's halo");
       P.ncol = upload_rows(false, 1);
@@ -467,98 +596,19 @@ int count_partitioned(m4_ctx* c, const m4_csr* g, const m4_opts* o, uint64_t out
   t_phase[1] = now_ms() - t_mark;
   t_mark = now_ms();
   // ---- 4. 4-cycle anchor over owner ranges with lower halos cut below hi
+  // (owners below r1 have degree <= 1 and no 4-cycle)
   {
     const size_t cap_rows = D.cap > fixed_used + c4_tmp ? D.cap - fixed_used - c4_tmp : 0;
-    // for every lower neighbour v of an owner u, the entries of row v up to
-    // and including u: u sits at position j of row v's upper part, and v's
-    // slot in u's lower part is the count of lower neighbours of u below v,
-    // so one ascending sweep over the rows fills every slot.  Each host thread
-    // sweeps all rows for the owners of its own share (balanced by lower
-    // entries), keeping per-owner cursors.
     const double tq = now_ms();
-    std::vector<int64_t> lptr(n + 1, 0);
-    for (int64_t u = 0; u < n; u++) lptr[u + 1] = lptr[u] + (u >= C.r1 ? H.dlo[u] : 0);
-    std::vector<int32_t> ulen((size_t)lptr[n] + 1);
-    {
-      std::vector<int64_t> cut(nthreads + 1, n);
-      cut[0] = C.r1;
-      for (int t = 1; t < nthreads; t++)
-        cut[t] = std::lower_bound(lptr.begin(), lptr.end(), lptr[n] * t / nthreads) - lptr.begin();
-      for (int t = 1; t <= nthreads; t++) cut[t] = std::max(cut[t], cut[t - 1]);
-      parallel_for(nthreads, nthreads, [&](int64_t a, int64_t b) {
-        for (int64_t t = a; t < b; t++) {
-          const int64_t ua = cut[t], ube = cut[t + 1];
-          if (ua >= ube) continue;
-          std::vector<int32_t> cur(ube - ua, 0);
-          // rows below ua cannot hold an owner of this share in their upper part
-          for (int64_t v = 0; v < ube; v++) {
-            const int32_t* rb = hc + H.nptr[v];
-            int32_t j = H.dlo[v];
-            const int32_t e = H.dr[v];
-            if (e - j > 16) j = (int32_t)(std::lower_bound(rb + j, rb + e, (int32_t)ua) - rb);
-            for (; j < e; j++) {
-              const int32_t u = rb[j];
-              if (u >= ube) break;
-              if (u < ua) continue;
-              ulen[lptr[u] + cur[u - ua]++] = j + 1;
-            }
-          }
-        }
-      });
-    }
+    C4Planner plan(HR, C.r1, nthreads);
     t_host += now_ms() - tq;
-    // per vertex: the range that holds its row (stamp) and the stored length
-    struct Held {
-      uint32_t stamp;
-      int32_t len;
-    };
-    std::vector<Held> held(n, Held{0, 0});
-    uint32_t rstamp = 0;
     int64_t lo = C.r1;
-    // owners below r1 have degree <= 1 and no 4-cycle
     while (lo < n) {
-      rstamp++;
-      rows.clear();
-      std::vector<int32_t> members;
-      // alignment of the descriptor arrays in the scratch region
-      size_t bytes = 512;
-      int64_t hi = lo;
       const double tp = now_ms();
-      while (hi < n) {
-        const int64_t u = hi;
-        const int64_t ub = H.nptr[u];
-        const int32_t dl = H.dlo[u];
-        const int32_t* lu = ulen.data() + lptr[u];
-        // a held row v in L(u) gains the entry u when the upper end moves past
-        // u; a new one is stored up to and including u; u's own lower part
-        // joins (its later entries come as the end moves on)
-        size_t add = (size_t)dl * 4 + 32 + (size_t)dl * 16 + 4;
-        constexpr int kAhead = 16;  // held[] is far larger than the caches
-        for (int32_t j = 0; j < dl; j++) {
-          if (j + kAhead < dl) __builtin_prefetch(&held[hc[ub + j + kAhead]]);
-          const Held& h = held[hc[ub + j]];
-          add += h.stamp == rstamp ? 4 : (size_t)lu[j] * 4 + 32;
-        }
-        if (bytes + add > cap_rows && hi > lo) break;
-        bytes += add;
-        for (int32_t j = 0; j < dl; j++) {
-          const int32_t v = hc[ub + j];
-          Held& h = held[v];
-          if (h.stamp == rstamp) {
-            h.len++;
-          } else {
-            h.stamp = rstamp;
-            h.len = lu[j];
-            members.push_back(v);
-          }
-        }
-        held[u] = Held{rstamp, dl};
-        members.push_back((int32_t)u);
-        hi++;
-      }
+      size_t bytes = 0;
+      const int64_t hi = plan.next(lo, cap_rows, rows, bytes);
       t_host += now_ms() - tp;
       if (bytes > cap_rows) throw Fail(M4_ENOMEM, "device budget below one owner's halo");
-      for (int32_t v : members) rows.push_back({v, 0, held[v].len});
       P.ncol = upload_rows(true, 0);
       P.row_len = rowlen;
       P.own_lo = lo;
@@ -629,3 +679,64 @@ int count_partitioned(m4_ctx* c, const m4_csr* g, const m4_opts* o, uint64_t out
 }
 
 }  // namespace m4
+
+extern "C" int m4_plan_partitions(int kind, int64_t n, const int64_t* nptr, const int32_t* col,
+                                  const int32_t* dlo, const int32_t* dplus, int64_t r1,
+                                  uint64_t cap_bytes, int64_t max_ranges, int64_t max_rows,
+                                  int64_t* range_end, int64_t* range_rows, int32_t* rows_v,
+                                  int64_t* rows_first, int32_t* rows_len, int64_t* nranges) {
+  using namespace m4;
+  if ((kind != 0 && kind != 1) || n < 0 || !nranges || (n > 0 && (!nptr || !col || !dlo || !dplus)))
+    return M4_EINVAL;
+  if (kind == 1 && (r1 < 0 || r1 > n)) return M4_EINVAL;
+  try {
+    std::vector<int32_t> dr(n);
+    for (int64_t v = 0; v < n; v++) dr[v] = (int32_t)(nptr[v + 1] - nptr[v]);
+    HostRows H;
+    H.n = n;
+    H.nptr = nptr;
+    H.col = col;
+    H.dr = dr.data();
+    H.dlo = dlo;
+    H.dplus = dplus;
+    std::vector<RowPart> rows;
+    int64_t k = 0, nr = 0;
+    auto emit = [&](int64_t hi, size_t bytes) -> int {
+      if (bytes > cap_bytes) return M4_ENOMEM;
+      if (k >= max_ranges || nr + (int64_t)rows.size() > max_rows) return M4_ERANGE;
+      range_end[k] = hi;
+      for (const RowPart& r : rows) {
+        rows_v[nr] = r.v;
+        rows_first[nr] = r.first;
+        rows_len[nr] = r.len;
+        nr++;
+      }
+      range_rows[k] = nr;
+      k++;
+      return M4_OK;
+    };
+    int rc = M4_OK;
+    if (kind == 0) {
+      TriPlanner plan(H);
+      for (int64_t lo = 0; lo < n && rc == M4_OK;) {
+        size_t bytes = 0;
+        const int64_t hi = plan.next(lo, cap_bytes, rows, bytes);
+        rc = emit(hi, bytes);
+        lo = hi;
+      }
+    } else {
+      C4Planner plan(H, r1, host_threads());
+      for (int64_t lo = r1; lo < n && rc == M4_OK;) {
+        size_t bytes = 0;
+        const int64_t hi = plan.next(lo, cap_bytes, rows, bytes);
+        rc = emit(hi, bytes);
+        lo = hi;
+      }
+    }
+    *nranges = k;
+    return rc;
+  } catch (const std::bad_alloc&) {
+    return M4_ENOMEM;
+  }
+}
+

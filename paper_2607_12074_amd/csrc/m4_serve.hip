@@ -8,12 +8,18 @@
 // lanes overlap on the device); a graph larger than one workgroup's share
 // goes to a worker thread that runs the multi-kernel single-graph path on its
 // own context and stream.  Whenever a lane's launch completes its results are
-// published, its memory is released and the next requests are admitted, so
-// requests arriving while others run join as soon as a lane and memory free
-// up.  Admission is strictly first-come first-served (no request overtakes
-// an earlier one that does not fit yet), which rules out starvation.
+// published and the next requests are admitted, so requests arriving while
+// others run join as soon as a lane and memory free up.  Admission counts
+// the device memory the server holds: every lane's arena (kept for the next
+// launches, and counted at the size the next launch grows it to), the
+// worker context's workspaces as its last job left them (at least the
+// running job's reserve); when the next request does not fit, idle lanes'
+// arenas and an idle worker's workspaces are freed first.  Admission is strictly first-come first-served (no request
+// overtakes an earlier one that does not fit yet), which rules out
+// starvation.
 #include <string.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -51,7 +57,7 @@ struct Lane {
   std::vector<Req*> reqs;
   std::vector<int64_t> voff, eoff, rowp;
   std::vector<int32_t> col;
-  uint64_t bytes = 0;
+  uint64_t need = 0;  // device bytes of the running launch
   bool busy = false;
 };
 
@@ -83,7 +89,9 @@ struct m4_server {
   std::deque<m4::Req*> queue;
   std::deque<m4::Req*> results;
   uint64_t next_id = 1, submitted = 0, completed = 0;
-  uint64_t inflight_bytes = 0, max_inflight_bytes = 0, launches = 0;
+  uint64_t inflight_bytes = 0, launches = 0;
+  uint64_t big_retained = 0;     // workspaces the worker context keeps between jobs
+  uint64_t max_device_bytes = 0;  // largest device memory held at once
   bool stop = false;
   m4::Lane lanes[m4::kLanes];
   std::thread sched, worker;
@@ -146,6 +154,44 @@ void collect_lane(m4_server* s, Lane& L) {
   L.busy = false;
 }
 
+// Device memory the server holds now: lane arenas (at least the running
+// launch's), the worker's workspaces (at least the running job's reserve)
+// and the lanes' planning context.
+uint64_t held_bytes(const m4_server* s) {
+  uint64_t h = s->ctx->held_bytes();
+  for (const Lane& L : s->lanes) h += std::max<uint64_t>(L.buf.dev.cap, L.busy ? L.need : 0);
+  h += s->big_busy ? std::max(s->big_retained, s->big_job->footprint) : s->big_retained;
+  return h;
+}
+
+// Frees what idle lanes and an idle worker keep; true if anything was freed.
+bool release_idle(m4_server* s) {
+  bool freed = false;
+  for (Lane& L : s->lanes)
+    if (!L.busy && L.buf.dev.cap > 0) {
+      (void)hipStreamSynchronize(L.stream);
+      L.buf.dev.release();
+      freed = true;
+    }
+  if (!s->big_busy && s->big_retained > 0) {
+    s->big_ctx->release_resident();
+    s->big_retained = s->big_ctx->held_bytes();
+    freed = true;
+  }
+  return freed;
+}
+
+uint64_t lane_need(int64_t G, int64_t sum_n, int64_t sum_nnz) {
+  return batch_layout(G, sum_n, sum_nnz, true).need;
+}
+
+// a lane arena's size after a launch that needs `need` bytes (DevBuf::ensure
+// grows by an eighth plus 1 MiB, so that slowly growing batches do not
+// reallocate every launch)
+uint64_t lane_cap_after(uint64_t cap, uint64_t need) {
+  return need <= cap ? cap : need + need / 8 + (1u << 20);
+}
+
 void scheduler(m4_server* s) {
   (void)hipSetDevice(s->ctx->device);
   std::unique_lock<std::mutex> lk(s->mu);
@@ -168,7 +214,8 @@ void scheduler(m4_server* s) {
     // admission, first come first served
     while (!s->queue.empty()) {
       Req* r = s->queue.front();
-      if (r->footprint > s->budget) {
+      const uint64_t alone = r->big ? r->footprint : lane_need(1, r->n, r->nnz);
+      if (alone + s->ctx->held_bytes() > s->budget) {
         s->queue.pop_front();
         r->status = M4_ENOMEM;
         r->t_admit = s->now();
@@ -177,14 +224,18 @@ void scheduler(m4_server* s) {
         progress = true;
         continue;
       }
-      if (s->inflight_bytes + r->footprint > s->budget) break;
       if (r->big) {
         if (s->big_busy) break;
+        auto after = [&] {
+          return held_bytes(s) - s->big_retained + std::max(s->big_retained, r->footprint);
+        };
+        if (after() > s->budget && !(release_idle(s) && after() <= s->budget)) break;
         s->queue.pop_front();
         r->t_admit = s->now();
         s->inflight_bytes += r->footprint;
         s->big_job = r;
         s->big_busy = true;
+        s->max_device_bytes = std::max(s->max_device_bytes, held_bytes(s));
         s->cv_big.notify_one();
         progress = true;
         continue;
@@ -199,17 +250,32 @@ void scheduler(m4_server* s) {
       // consecutive small requests that fit join this launch
       Lane& L = *free_lane;
       L.reqs.clear();
+      int64_t sn = 0, snnz = 0;
+      bool retried = false;
       while (!s->queue.empty() && (int)L.reqs.size() < kMaxBatchGraphs) {
         Req* q = s->queue.front();
-        if (q->big || q->footprint > s->budget ||
-            s->inflight_bytes + q->footprint > s->budget)
+        if (q->big) break;
+        const uint64_t need = lane_need((int64_t)L.reqs.size() + 1, sn + q->n, snnz + q->nnz);
+        const uint64_t after = held_bytes(s) - L.buf.dev.cap + lane_cap_after(L.buf.dev.cap, need);
+        if (after > s->budget) {
+          // the first request of a launch may make room by freeing idle memory
+          if (L.reqs.empty() && !retried) {
+            retried = true;
+            if (release_idle(s)) continue;
+          }
           break;
+        }
         s->queue.pop_front();
         q->t_admit = s->now();
         s->inflight_bytes += q->footprint;
         L.reqs.push_back(q);
+        sn += q->n;
+        snnz += q->nnz;
+        L.need = need;
       }
-      if (s->inflight_bytes > s->max_inflight_bytes) s->max_inflight_bytes = s->inflight_bytes;
+      if (L.reqs.empty()) break;
+      L.busy = true;
+      s->max_device_bytes = std::max(s->max_device_bytes, held_bytes(s));
       lk.unlock();
       bool ok = true;
       try {
@@ -228,7 +294,6 @@ void scheduler(m4_server* s) {
       }
       progress = true;
     }
-    if (s->inflight_bytes > s->max_inflight_bytes) s->max_inflight_bytes = s->inflight_bytes;
     if (s->completed == s->submitted) s->cv_done.notify_all();
     bool any_busy = s->big_busy;
     for (Lane& L : s->lanes) any_busy |= L.busy;
@@ -258,10 +323,14 @@ void big_worker(m4_server* s) {
     g.row_ptr = r->rp.data();
     g.col = r->col.data();
     g.on_device = 0;
+    // the job runs within the reserve it was admitted with (the resident
+    // path when that holds it, else halo partitions)
     m4_opts o{};
-    o.device_budget_bytes = 0;
+    o.device_budget_bytes = r->footprint;
     const int rc = m4_count_motifs4_ex(s->big_ctx, &g, &o, r->counts, nullptr);
+    const uint64_t kept = s->big_ctx->held_bytes();
     lk.lock();
+    s->big_retained = kept;
     r->status = rc;
     s->big_finished = true;
     s->cv.notify_all();
@@ -374,7 +443,7 @@ extern "C" int m4_server_stats(const m4_server* s, uint64_t* max_inflight_bytes,
   if (!s) return M4_EINVAL;
   m4_server* m = const_cast<m4_server*>(s);
   std::lock_guard<std::mutex> lk(m->mu);
-  if (max_inflight_bytes) *max_inflight_bytes = m->max_inflight_bytes;
+  if (max_inflight_bytes) *max_inflight_bytes = m->max_device_bytes;
   if (launches) *launches = m->launches;
   if (completed) *completed = m->completed;
   return M4_OK;

@@ -36,14 +36,21 @@ def test_mix_equals_alone(ctx):
     import paper_2607_12074_amd as m4
     graphs = [gg.serve_graph(i, seed=21) for i in range(48)]
     graphs += [gg.rmat(14, 8, 0.57, 0.19, 0.19, 1), G.wheel(20000)]  # beyond one workgroup
-    srv = m4.Server(ctx, 2 << 30)
+    import torch
+    budget = 512 << 20
+    free0, _ = torch.cuda.mem_get_info(0)
+    srv = m4.Server(ctx, budget)
     ids = {}
     for i, g in enumerate(graphs):
         ids[srv.submit(*g, tag=i)] = i
     res = _collect(srv, len(graphs))
     st = srv.stats()
+    # lane arenas and the worker's workspaces are kept after the work: device
+    # memory really allocated (hipMalloc, outside torch's cache)
+    free1, _ = torch.cuda.mem_get_info(0)
     srv.close()
-    assert st["max_inflight_bytes"] <= 2 << 30 and st["launches"] >= 1
+    assert st["max_inflight_bytes"] <= budget and st["launches"] >= 1
+    assert free0 - free1 <= budget + (2 << 20), (free0 - free1, budget)
     for rid, r in res.items():
         i = ids[rid]
         assert r["tag"] == i and r["status"] == 0
@@ -55,16 +62,22 @@ def test_mix_equals_alone(ctx):
 
 def test_tight_budget_serialises_and_rejects(ctx):
     import paper_2607_12074_amd as m4
+    import torch
     graphs = [gg.batch_graph(i, seed=4) for i in range(40)]
     budget = 16 << 20
+    free0, _ = torch.cuda.mem_get_info(0)
     srv = m4.Server(ctx, budget)
     ids = [srv.submit(*g, tag=i) for i, g in enumerate(graphs)]
     big = gg.rmat(16, 16, 0.57, 0.19, 0.19, 2)  # needs more than the budget
     big_id = srv.submit(*big, tag=999)
     res = _collect(srv, len(ids) + 1)
     st = srv.stats()
+    # what the server keeps after the work (lane arenas, worker workspaces)
+    # is device memory really allocated (hipMalloc, outside torch's cache)
+    free1, _ = torch.cuda.mem_get_info(0)
     srv.close()
     assert st["max_inflight_bytes"] <= budget
+    assert free0 - free1 <= budget + (2 << 20), (free0 - free1, budget)
     assert res[big_id]["status"] == m4.M4_ENOMEM
     for rid, g in zip(ids, graphs):
         assert res[rid]["status"] == 0 and res[rid]["counts"] == ctx.count(*g)
