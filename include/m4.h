@@ -71,6 +71,13 @@ typedef struct {
                                    one after the other on one stream (by default
                                    they overlap on two streams, except when
                                    4-cycle owners are binned)                      */
+#define M4_BASIS_WEDGE 0x80u    /* single graph: count 4-cycles with degree-ordered
+                                   wedges, each at its highest vertex            */
+#define M4_BASIS_EDGE 0x100u    /* single graph: count 4-cycles and 4-paths from
+                                   edge anchors, the adjacent pairs of A_e x B_e
+                                   (Section III-F); resident calls only.  With
+                                   neither flag the anchor-selection objective
+                                   of Section III-A chooses per graph            */
 #define M4_PLAIN_LOOP 0x20u     /* m4_count_batch: one single-graph call per graph
                                    (the reference point of the batched launch)     */
 
@@ -104,6 +111,7 @@ enum {
   M4_K_TRI_HUBS,      /* hub tables of the long out-lists (triangle probes)     */
   M4_K_C4_DESC,       /* 4-cycle window owners' segment descriptors             */
   M4_K_C4_BIN,        /* 4-cycle owners binned by counter window                */
+  M4_K_EDGE,          /* edge-anchor basis: adjacent pairs of A_e x B_e         */
   M4_NK = 16
 };
 
@@ -121,6 +129,8 @@ enum {
  *                   an owner counted in rank ranges reads its rows once per
  *                   pass) or row entries read by the histogram and scatter
  *                   passes (binned slot)
+ *   edge basis:     k_elems = row entries scanned, k_rows = owners with an
+ *                   out-neighbour, k_aux = (out-neighbour, neighbour) pairs
  *   closure:        k_elems = oriented edges, k_rows = vertices
  *   build:          k_elems = CSR entries, k_rows = vertices */
 typedef struct {
@@ -150,6 +160,11 @@ typedef struct {
    * gathering their halo rows into pinned memory (ms_build, ms_tri, ms_c4 and
    * ms_closure then hold the wall time of each phase)                        */
   double ms_host;
+  /* cycle/path anchor basis of a resident call: 0 degree-ordered wedges,
+   * 1 edge anchors (A_e x B_e); the anchor-selection objective's estimate of
+   * each, in ns (the edge basis is infinite under a device budget)          */
+  uint32_t basis_used;
+  double cost_wedge, cost_edge;
 } m4_stats;
 
 typedef struct m4_ctx m4_ctx;

@@ -23,10 +23,11 @@ M4_OK, M4_EINVAL, M4_ERANGE, M4_EOVERFLOW, M4_ENOMEM, M4_EDEVICE, M4_EBUSY, M4_E
 M4_VALIDATE, M4_NO_CACHE, M4_FORCE_PARTITION, M4_STATS, M4_TIMING = 0x1, 0x2, 0x4, 0x8, 0x10
 M4_PLAIN_LOOP = 0x20
 M4_SERIAL = 0x40
+M4_BASIS_WEDGE, M4_BASIS_EDGE = 0x80, 0x100
 M4_NK = 16
 KERNELS = ("build", "tri_global", "tri_1024", "tri_512", "tri_256", "tri_128", "tri_wave",
            "c4_plan", "c4_window", "c4_med", "c4_hash", "closure", "tri_hubs", "c4_desc",
-           "c4_bin")
+           "c4_bin", "edge")
 NAMES = ("star", "path", "paw", "cycle", "diamond", "clique")
 BASIS = ("T", "K4", "C4_ni", "S", "P_ni", "Paw_ni", "D_ni", "sum_t")
 
@@ -61,7 +62,9 @@ class Stats(ctypes.Structure):
                 ("ms_total", ctypes.c_double), ("ms_build", ctypes.c_double),
                 ("ms_tri", ctypes.c_double), ("ms_c4", ctypes.c_double),
                 ("ms_closure", ctypes.c_double), ("ms_h2d", ctypes.c_double),
-                ("device_bytes", ctypes.c_uint64), ("ms_host", ctypes.c_double)]
+                ("device_bytes", ctypes.c_uint64), ("ms_host", ctypes.c_double),
+                ("basis_used", ctypes.c_uint32), ("cost_wedge", ctypes.c_double),
+                ("cost_edge", ctypes.c_double)]
 
     def to_dict(self):
         d = {k: int(v) for k, v in zip(BASIS, self.basis)}

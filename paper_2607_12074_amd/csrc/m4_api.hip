@@ -286,6 +286,8 @@ void run_resident(m4_ctx* c, const int64_t* rp, const int32_t* col, int64_t n, i
   if (kt) kt->begin(M4_K_BUILD, s);
   build_prep(rp, col, n, nnz, (flags & M4_VALIDATE) != 0, P, C, c->scal, c->scal_host, a, s);
   if (kt) kt->end(M4_K_BUILD, s);
+  // the cycle/path anchor basis (Section III-A): wedges or edge anchors
+  c->basis = choose_basis(P, tu, flags, o && o->device_budget_bytes > 0, c->scal, c->cost_pair, s);
   if (want_timing) M4_HIP(hipEventRecord(c->ev[1], s));
   auto big = [c, s](size_t bytes) -> char* {
     c->big.ensure(bytes, s);
@@ -311,7 +313,8 @@ void run_resident(m4_ctx* c, const int64_t* rp, const int32_t* col, int64_t n, i
   ac.cap = c4_bytes;
   Launch tri = tri_plan(P, c->scal, tu, flags, cache_rows, at, s, c->num_cu, big, kt);
   bool binned = false;
-  Launch c4 = c4_plan(P, C, c->scal, tu, flags, ac, s, c->num_cu, kt, big2, &binned);
+  Launch c4 = c->basis.edge ? edge_plan(P, c->scal, flags, c->num_cu, kt)
+                            : c4_plan(P, C, c->scal, tu, flags, ac, s, c->num_cu, kt, big2, &binned);
   if ((flags & M4_SERIAL) || binned) {
     tri(s);
     if (want_timing) M4_HIP(hipEventRecord(c->ev[2], s));
@@ -328,7 +331,7 @@ void run_resident(m4_ctx* c, const int64_t* rp, const int32_t* col, int64_t n, i
   if (want_timing) M4_HIP(hipEventRecord(c->ev[3], s));
   if (kt) kt->begin(M4_K_CLOSURE, s);
   closure_run(P, c->scal, flags, s);
-  finalize_run(c->scal, s);
+  finalize_run(c->scal, s, c->basis.edge);
   if (kt) kt->end(M4_K_CLOSURE, s);
   if (want_timing) M4_HIP(hipEventRecord(c->ev[4], s));
 }
@@ -340,6 +343,9 @@ void fill_stats(m4_ctx* c, const Scal& h, m4_stats* st, bool timing) {
   st->wedges = h.stat[ST_WEDGES];
   st->cache_lookups = h.stat[ST_LOOKUPS];
   st->cache_hits = h.stat[ST_HITS];
+  st->basis_used = c->basis.edge ? 1u : 0u;
+  st->cost_wedge = c->basis.cost_wedge;
+  st->cost_edge = c->basis.cost_edge;
   for (int k = 0; k < M4_NK; k++) {
     st->k_elems[k] = h.kstat[k][0];
     st->k_rows[k] = h.kstat[k][1];

@@ -60,13 +60,24 @@ __global__ __launch_bounds__(CL_NT) void k_closure(const int64_t* __restrict__ n
 }
 
 // status: 0 ok, 3 a count >= 2^64, 7 internal check failed
-__global__ void k_finalize(Scal* scal) {
+__global__ void k_finalize(Scal* scal, int zbasis) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const u128_t in[7] = {load_u128(&scal->acc[ACC_K4]), load_u128(&scal->acc[ACC_C4]),
-                        load_u128(&scal->acc[ACC_S]),  load_u128(&scal->acc[ACC_P]),
-                        load_u128(&scal->acc[ACC_D]),  load_u128(&scal->acc[ACC_PAW2]),
-                        load_u128(&scal->acc[ACC_SUMT])};
-  scal->status = finalize_basis(in, scal->out, scal->basis);
+  const u128_t K4 = load_u128(&scal->acc[ACC_K4]), D = load_u128(&scal->acc[ACC_D]);
+  u128_t C4 = load_u128(&scal->acc[ACC_C4]);
+  int zstatus = 0;
+  if (zbasis) {
+    // edge-anchor basis: Z = 4 * cycle (each induced 4-cycle is an adjacent
+    // pair of A_e x B_e for each of its four edges), and a 4-cycle subgraph
+    // is an induced 4-cycle, a diamond (D_ni - 6 K4) or one of the three in
+    // a 4-clique
+    const u128_t Z = load_u128(&scal->acc[ACC_Z]);
+    if (Z % 4 != 0 || D < 3 * K4) zstatus = 7;
+    else C4 = Z / 4 + D - 3 * K4;
+  }
+  const u128_t in[7] = {K4, C4, load_u128(&scal->acc[ACC_S]), load_u128(&scal->acc[ACC_P]), D,
+                        load_u128(&scal->acc[ACC_PAW2]), load_u128(&scal->acc[ACC_SUMT])};
+  const int st = finalize_basis(in, scal->out, scal->basis);
+  scal->status = zstatus ? zstatus : st;
 }
 
 }  // namespace
@@ -81,6 +92,8 @@ void closure_run(const Prep& P, Scal* scal, uint32_t flags, hipStream_t s) {
                                                lo, hi, scal);
 }
 
-void finalize_run(Scal* scal, hipStream_t s) { k_finalize<<<1, 64, 0, s>>>(scal); }
+void finalize_run(Scal* scal, hipStream_t s, bool zbasis) {
+  k_finalize<<<1, 64, 0, s>>>(scal, zbasis ? 1 : 0);
+}
 
 }  // namespace m4

@@ -70,6 +70,8 @@ struct m4_ctx {
   std::string last_error;
   m4::BatchState* batch = nullptr;
   m4::PartState* part = nullptr;
+  m4::BasisChoice basis;                  // cycle/path basis of the last resident count
+  unsigned long long cost_pair[2] = {0, 0};  // its objective's inputs, read back
   // device bytes the context holds now (workspaces, batch buffers, Scal)
   size_t held_bytes() const;
   // frees every workspace except the budgeted path's (c->extra)

@@ -23,7 +23,12 @@ struct U128 {
 };
 
 enum Acc { ACC_K4 = 0, ACC_C4, ACC_S, ACC_P, ACC_PAW2, ACC_D, ACC_SUMT, ACC_N };
-enum Stat { ST_STEPS = 0, ST_WEDGES, ST_LOOKUPS, ST_HITS, ST_N = 8 };
+// adjacent pairs of A_e x B_e over all edges (edge-anchor basis), in the
+// spare accumulator
+constexpr int ACC_Z = ACC_N;
+// ST_COST, ST_COST + 1: the anchor-selection inputs (wedge endpoints bound,
+// edge-basis row entries)
+enum Stat { ST_STEPS = 0, ST_WEDGES, ST_LOOKUPS, ST_HITS, ST_COST, ST_N = 8 };
 
 // Triangle-owner buckets by out-degree k = d+(u).
 enum TriBucket { TB_NONE = 0, TB_WAVE, TB_LDS, TB_GLOBAL, TB_N = 4 };
@@ -120,6 +125,11 @@ struct Tuning {
   int c4_bin_win = 6;       // owners above the one-pass medium bound whose endpoints span at
                             // least this many counter windows are binned by window (0: never)
   int c4_bin_cap = 0;       // endpoints of a binning workgroup's scratch (0: 2^20)
+  // weights of the anchor-selection objective, from stage times measured on
+  // the MI355X over graphs of 10^2 to 10^7 edges: ns per wedge endpoint
+  // bound, fixed us of the wedge stage (its plan kernels and host
+  // read-backs), ns per row entry the edge basis scans
+  double cost_wedge_ns = 0.005, cost_wedge_fixed_us = 300.0, cost_edge_ns = 0.03;
 };
 
 // Optional per-launch HIP event pairs (M4_TIMING).
@@ -224,6 +234,16 @@ inline void tri_run(const Prep& P, Scal* scal, const Tuning& tu, uint32_t flags,
   tri_plan(P, scal, tu, flags, cache_rows, tmp, s, num_cu, big_scratch, kt)(s);
 }
 
+// m4_edge.hip: the cycle/path anchor basis chosen by the anchor-selection
+// objective (estimates in ns; edge = adjacent pairs of A_e x B_e)
+struct BasisChoice {
+  bool edge = false;
+  double cost_wedge = 0, cost_edge = 0;
+};
+BasisChoice choose_basis(const Prep& P, const Tuning& tu, uint32_t flags, bool budgeted,
+                         Scal* scal, unsigned long long* host_pair, hipStream_t s);
+Launch edge_plan(const Prep& P, Scal* scal, uint32_t flags, int num_cu, KTimer* kt);
+
 // m4_c4.hip (binned, if given, is set when owners go to the binning kernel,
 // which holds every CU with persistent workgroups and all of their LDS)
 Launch c4_plan(const Prep& P, const Classes& C, Scal* scal, const Tuning& tu, uint32_t flags,
@@ -237,6 +257,7 @@ inline void c4_run(const Prep& P, const Classes& C, Scal* scal, const Tuning& tu
 
 // m4_closure.hip
 void closure_run(const Prep& P, Scal* scal, uint32_t flags, hipStream_t s);
-void finalize_run(Scal* scal, hipStream_t s);
+// zbasis: the 4-cycle statistic is Z of the edge-anchor basis, not C4_ni
+void finalize_run(Scal* scal, hipStream_t s, bool zbasis = false);
 
 }  // namespace m4

@@ -674,6 +674,8 @@ int count_partitioned(m4_ctx* c, const m4_csr* g, const m4_opts* o, uint64_t out
     st->ms_closure = t_phase[3];
     st->ms_host = t_host;
     st->device_bytes = c->held_bytes();
+    st->basis_used = 0;  // halo partitions hold 1-hop rows: the wedge basis
+    st->cost_wedge = st->cost_edge = 0;
   }
   return M4_OK;
 }

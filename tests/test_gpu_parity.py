@@ -25,8 +25,12 @@ def ctx():
 
 
 def test_closed_forms(ctx):
+    # by the basis the anchor-selection objective picks (the edge basis for
+    # most of these small graphs) and by the wedge basis
+    import paper_2607_12074_amd as m4
     for name, make, exp in CLOSED:
         assert ctx.count(*make()) == exp, name
+        assert ctx.count(*make(), flags=m4.M4_BASIS_WEDGE) == exp, name
 
 
 def cocktail_party(k):
@@ -92,23 +96,30 @@ def _random_cases():
 
 
 def test_random_graphs_vs_oracle(ctx):
+    import paper_2607_12074_amd as m4
     for i, g in enumerate(_random_cases()):
-        assert ctx.count(*g) == oracle.closure(*g), i
+        ref = oracle.closure(*g)
+        assert ctx.count(*g) == ref, i
+        assert ctx.count(*g, flags=m4.M4_BASIS_WEDGE) == ref, i
 
 
 def test_small_graphs_vs_brute_force(ctx):
     for s in range(20):
         g = G.gnp(9 + s % 12, 0.3, 900 + s)
-        assert ctx.count(*g) == oracle.brute(*g), s
+        ref = oracle.brute(*g)
+        assert ctx.count(*g) == ref, s
+        assert ctx.count(*g, flags=__import__("paper_2607_12074_amd").M4_BASIS_WEDGE) == ref, s
 
 
 def test_er_workload_golden(ctx):
     gold = json.load(open(os.path.join(HERE, "golden", "er_2000_20000.json")))
     g = gg.er_c1(seed=1)
-    counts, st = ctx.count(*g, stats=True)
-    assert list(counts) == gold["counts"]
-    for k, v in gold["basis"].items():
-        assert st[k] == v, k
+    import paper_2607_12074_amd as m4
+    for fl in (0, m4.M4_BASIS_WEDGE, m4.M4_BASIS_EDGE):
+        counts, st = ctx.count(*g, flags=fl, stats=True)
+        assert list(counts) == gold["counts"], fl
+        for k, v in gold["basis"].items():
+            assert st[k] == v, (fl, k)
 
 
 def test_batch_golden_graphs_single(ctx):
@@ -169,7 +180,7 @@ def test_medium_bucket_rank_ranges(ctx):
             seen = []
             for md, mw in ((-1, 0), (12288, 0), (12288, 1)):
                 ctx.set_tuning(c4_med_win=mw)
-                got, st = ctx.count(*g, c4_med_max=md, stats=True)
+                got, st = ctx.count(*g, c4_med_max=md, flags=m4.M4_BASIS_WEDGE, stats=True)
                 assert got == ref, (md, mw)
                 seen.append(st["k_rows"][med])
             assert seen[0] == 0 and seen[2] > seen[1]
@@ -183,10 +194,10 @@ def test_serial_and_overlapped_stages_agree(ctx):
     import paper_2607_12074_amd as m4
     g = gg.rmat(16, 12, 0.57, 0.19, 0.19, 23)
     ref = oracle.closure(*g)
-    b, sb = ctx.count(*g, flags=m4.M4_SERIAL, stats=True)
+    b, sb = ctx.count(*g, flags=m4.M4_SERIAL | m4.M4_BASIS_WEDGE, stats=True)
     assert b == ref
     for _ in range(3):
-        a, sa = ctx.count(*g, stats=True)
+        a, sa = ctx.count(*g, flags=m4.M4_BASIS_WEDGE, stats=True)
         assert a == ref
         for k in ("T", "K4", "C4_ni", "S", "P_ni", "Paw_ni", "D_ni", "sum_t", "wedges",
                   "intersect_steps", "cache_lookups"):
@@ -306,7 +317,7 @@ def test_binned_four_cycle_owners(ctx):
             ref = oracle.closure(*g)
             for bw, cap in ((1, 0), (1, 1000), (1, 64), (2, 0), (0, 0)):
                 ctx.set_tuning(c4_bin_win=bw, c4_bin_cap=cap)
-                got, st = ctx.count(*g, stats=True)
+                got, st = ctx.count(*g, flags=m4.M4_BASIS_WEDGE, stats=True)
                 assert got == ref, (bw, cap)
                 if bw == 0:
                     assert st["k_rows"][slot] == 0
