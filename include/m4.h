@@ -162,7 +162,8 @@ typedef struct {
   double ms_host;
   /* cycle/path anchor basis of a resident call: 0 degree-ordered wedges,
    * 1 edge anchors (A_e x B_e); the anchor-selection objective's estimate of
-   * each, in ns (the edge basis is infinite under a device budget)          */
+   * each, in ns (for the edge basis a lower bound when that already exceeds
+   * the wedge estimate; infinite under a device budget)                     */
   uint32_t basis_used;
   double cost_wedge, cost_edge;
 } m4_stats;

@@ -40,23 +40,38 @@ __device__ __forceinline__ int64_t find_sorted(const int32_t* __restrict__ a, in
 // lower neighbour v of an owner lends its row but the owner), and the row
 // entries the edge basis scans, sum over u of d+(u) * sum over a in N(u) of
 // d(a) (each edge owned by its lower end scans the rows of the lower end's
-// neighbours).
-__global__ void k_edge_cost(const int64_t* __restrict__ nptr, const int32_t* __restrict__ ncol,
-                            const int32_t* __restrict__ dr, const int32_t* __restrict__ dplus,
+// neighbours).  The first pass reads degrees only and gives the wedge term
+// and a lower bound of the edge term (every neighbour has degree >= 1 and u
+// itself is in each neighbour's row: sum over u of d+(u) d(u)); the second
+// reads the rows and is run only when that bound does not settle the
+// choice.
+__global__ void k_edge_cost(const int32_t* __restrict__ dr, const int32_t* __restrict__ dplus,
                             int64_t n, unsigned long long* __restrict__ out) {
-  unsigned long long wedge = 0, scan = 0;
+  unsigned long long wedge = 0, lower = 0;
   for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
        u += (int64_t)gridDim.x * blockDim.x) {
     const int64_t d = dr[u];
     if (d >= 2) wedge += (unsigned long long)(d - 1) * (unsigned long long)dplus[u];
-    if (dplus[u] > 0) {
-      unsigned long long s = 0;
-      for (int64_t p = nptr[u]; p < nptr[u] + d; p++) s += (unsigned long long)dr[ncol[p]];
-      scan += s * (unsigned long long)dplus[u];
-    }
+    lower += (unsigned long long)d * (unsigned long long)dplus[u];
   }
   block_add_u64<256>(&out[0], wedge);
-  block_add_u64<256>(&out[1], scan);
+  block_add_u64<256>(&out[1], lower);
+}
+
+__global__ void k_edge_scan_cost(const int64_t* __restrict__ nptr,
+                                 const int32_t* __restrict__ ncol,
+                                 const int32_t* __restrict__ dr,
+                                 const int32_t* __restrict__ dplus, int64_t n,
+                                 unsigned long long* __restrict__ out) {
+  unsigned long long scan = 0;
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
+       u += (int64_t)gridDim.x * blockDim.x) {
+    if (dplus[u] == 0) continue;
+    unsigned long long sum = 0;
+    for (int64_t p = nptr[u]; p < nptr[u] + dr[u]; p++) sum += (unsigned long long)dr[ncol[p]];
+    scan += sum * (unsigned long long)dplus[u];
+  }
+  block_add_u64<256>(out, scan);
 }
 
 // Z over the edges owned by their lower end: one 256-thread workgroup per
@@ -113,13 +128,13 @@ __global__ __launch_bounds__(256) void k_edge_pairs(const int64_t* __restrict__ 
 BasisChoice choose_basis(const Prep& P, const Tuning& tu, uint32_t flags, bool budgeted,
                          Scal* scal, unsigned long long* host_pair, hipStream_t s) {
   BasisChoice b;
+  host_pair[0] = host_pair[1] = 0;
+  const bool forced = (flags & (M4_BASIS_WEDGE | M4_BASIS_EDGE)) != 0;
+  const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(std::max<int64_t>(P.n, 1), 256), 4096);
   if (P.n > 0) {
-    k_edge_cost<<<(unsigned)std::min<int64_t>(ceil_div(P.n, 256), 4096), 256, 0, s>>>(
-        P.nptr, P.ncol, P.dr, P.dplus, P.n, &scal->stat[ST_COST]);
+    k_edge_cost<<<grid, 256, 0, s>>>(P.dr, P.dplus, P.n, &scal->stat[ST_COST]);
     M4_HIP(hipMemcpyAsync(host_pair, &scal->stat[ST_COST], 16, hipMemcpyDeviceToHost, s));
     M4_HIP(hipStreamSynchronize(s));
-  } else {
-    host_pair[0] = host_pair[1] = 0;
   }
   // Eq. (1) over the two cycle/path bases: the triangle anchor, the
   // recoverable counts (closure yield: all six for both) and the reuse
@@ -129,7 +144,17 @@ BasisChoice choose_basis(const Prep& P, const Tuning& tu, uint32_t flags, bool b
   // wedge plan), and the halo term: the edge basis reads 2-hop rows, which
   // the halo partitions do not hold, so it is infinite under a budget.
   b.cost_wedge = tu.cost_wedge_ns * (double)host_pair[0] + tu.cost_wedge_fixed_us * 1e3;
-  b.cost_edge = budgeted ? INFINITY : tu.cost_edge_ns * (double)host_pair[1];
+  b.cost_edge = tu.cost_edge_ns * (double)host_pair[1];  // a lower bound so far
+  if (budgeted) {
+    b.cost_edge = INFINITY;
+  } else if (P.n > 0 && (b.cost_edge < b.cost_wedge || forced)) {
+    fill_u32(&scal->stat[ST_COST + 1], 0, 2, s);
+    k_edge_scan_cost<<<grid, 256, 0, s>>>(P.nptr, P.ncol, P.dr, P.dplus, P.n,
+                                          &scal->stat[ST_COST + 1]);
+    M4_HIP(hipMemcpyAsync(host_pair + 1, &scal->stat[ST_COST + 1], 8, hipMemcpyDeviceToHost, s));
+    M4_HIP(hipStreamSynchronize(s));
+    b.cost_edge = tu.cost_edge_ns * (double)host_pair[1];
+  }
   if (flags & M4_BASIS_EDGE) b.edge = !budgeted;
   else if (flags & M4_BASIS_WEDGE) b.edge = false;
   else b.edge = b.cost_edge < b.cost_wedge;
