@@ -870,8 +870,8 @@ constexpr int BF_GROUP = 192;    // scatter positions per group
 constexpr int BF_HBITS = BF_SHIFT - 1, BF_HSLOTS = 1 << BF_HBITS;  // 64-bit slots
 constexpr int BF_BIG = 4096;     // dense buckets above this: the whole block
 constexpr int BF_BIGLIST = 48;
-constexpr int BF_SB = 8;         // staging buffer entries per target (two 16-byte stores)
-constexpr int BF_NTS = 1032;     // targets with a staging buffer (12 words each)
+constexpr int BF_SB = 16;        // staging buffer entries per target (four 16-byte stores)
+constexpr int BF_NTS = 620;      // targets with a staging buffer (20 words each)
 static_assert((int64_t)C4_BIN_KMAX * C4_WIN_WORDS <= (int64_t)BF_KMAX * BF_WORDS,
               "a binned owner's fine buckets must fit the LDS histogram");
 static_assert(2 * BF_GROUP <= BF_HSLOTS / 2, "a hash group must keep its table half empty");
@@ -1217,11 +1217,11 @@ __global__ __launch_bounds__(BN_NT, 4) void k_c4_bin(C4Args A) {
       // than BF_GROUP endpoints alone (a dense target; it always ends its
       // stretch).  Each bucket's target goes to off; the scatter state sits in
       // the counter regions, unused until pass 3: per target its write
-      // cursor (bit 31: dense), and for the first BF_NTS targets an 8-entry
+      // cursor (bit 31: dense), and for the first BF_NTS targets a BF_SB-entry
       // staging buffer (its fill and completion counts, and a tail cursor for
       // endpoints that arrive while it is full).  Targets start at multiples
-      // of 8 scratch entries, so a full buffer leaves as two aligned 16-byte
-      // stores instead of eight scattered ones.
+      // of 8 scratch entries, so a full buffer leaves as aligned 16-byte
+      // stores instead of BF_SB scattered ones.
       uint32_t* head = cnt;
       uint32_t* tail = cnt + BF_KMAX;
       uint32_t* tend = tail + BF_NTS;
@@ -1309,16 +1309,20 @@ __global__ __launch_bounds__(BN_NT, 4) void k_c4_bin(C4Args A) {
           }
         }
         if (flush) {
-          // every slot of the buffer is written: two 16-byte loads, the
-          // counters reset, two aligned 16-byte stores
+          // every slot of the buffer is written: it leaves as aligned
+          // 16-byte stores, two at a time, and only then are the counters
+          // reset (no new entry lands in the buffer before that)
           const int4* sv = reinterpret_cast<const int4*>(stage + t * BF_SB);
-          const int4 v0 = sv[0], v1 = sv[1];
           const uint32_t at = atomicAdd(&head[t], (uint32_t)BF_SB) & 0x7fffffffu;
+          int4* dst = reinterpret_cast<int4*>(bins + at);
+#pragma unroll
+          for (int k = 0; k < BF_SB / 4; k += 2) {
+            const int4 v0 = sv[k], v1 = sv[k + 1];
+            dst[k] = v0;
+            dst[k + 1] = v1;
+          }
           done[t] = 0;
           fill[t] = 0;
-          int4* dst = reinterpret_cast<int4*>(bins + at);
-          dst[0] = v0;
-          dst[1] = v1;
         }
       });
       reads += (unsigned long long)total;

@@ -21,6 +21,10 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <condition_variable>
+#include <functional>
+#include <mutex>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -518,31 +522,30 @@ int count_partitioned(m4_ctx* c, const m4_csr* g, const m4_opts* o, uint64_t out
   HR.dr = H.dr.data();
   HR.dlo = H.dlo.data();
   HR.dplus = H.dplus.data();
-  auto upload_rows = [&](bool with_len, int64_t nptr_bias_dlo) -> int32_t* {
-    (void)nptr_bias_dlo;
+  // A range's rows gathered into a pinned buffer: (row, offset) pairs, stored
+  // prefix lengths, then the entries.
+  struct Staged {
+    int64_t lo = 0, hi = 0, nrows = 0, ent = 0;
+    int err = M4_OK;
+    std::string msg;
+  };
+  auto gather_rows = [&](const std::vector<RowPart>& rr, Pinned& S, Staged& st) {
     int64_t ent = 0;
-    for (const RowPart& r : rows) ent += r.len;
-    D.used = fixed_used;
-    int64_t* dpairs = D.take<int64_t>(2 * rows.size() + 2);
-    int32_t* dlens = D.take<int32_t>(rows.size() + 1);
-    int32_t* dcol = D.take<int32_t>(ent + NCOL_PAD);
-    Pinned& S = PS.stage[parts & 1];
-    const size_t sb = al((2 * rows.size() + 2) * 8) + al((rows.size() + 1) * 4) + al(ent * 4 + 4);
-    S.ensure(sb);
+    for (const RowPart& r : rr) ent += r.len;
+    const size_t nr = rr.size();
+    S.ensure(al((2 * nr + 2) * 8) + al((nr + 1) * 4) + al(ent * 4 + 4));
     int64_t* hp = reinterpret_cast<int64_t*>(S.p);
-    int32_t* hl = reinterpret_cast<int32_t*>(S.p + al((2 * rows.size() + 2) * 8));
-    int32_t* hcc = reinterpret_cast<int32_t*>(S.p + al((2 * rows.size() + 2) * 8) +
-                                              al((rows.size() + 1) * 4));
-    const double tg = now_ms();
+    int32_t* hl = reinterpret_cast<int32_t*>(S.p + al((2 * nr + 2) * 8));
+    int32_t* hcc = reinterpret_cast<int32_t*>(S.p + al((2 * nr + 2) * 8) + al((nr + 1) * 4));
     // row offsets in the buffer, then the copies on all host threads
     int64_t off = 0;
-    for (size_t i = 0; i < rows.size(); i++) {
+    for (size_t i = 0; i < nr; i++) {
       hp[2 * i + 1] = off;
-      off += rows[i].len;
+      off += rr[i].len;
     }
-    parallel_for((int64_t)rows.size(), nthreads, [&](int64_t a, int64_t b) {
+    parallel_for((int64_t)nr, nthreads, [&](int64_t a, int64_t b) {
       for (int64_t i = a; i < b; i++) {
-        const RowPart& r = rows[i];
+        const RowPart& r = rr[i];
         const int64_t o = hp[2 * i + 1];
         memcpy(hcc + o, hc + H.nptr[r.v] + r.first, (size_t)r.len * 4);
         hp[2 * i] = r.v;
@@ -550,15 +553,113 @@ int count_partitioned(m4_ctx* c, const m4_csr* g, const m4_opts* o, uint64_t out
         hl[i] = (int32_t)(r.first + r.len);  // stored prefix length (when the row starts at 0)
       }
     });
-    t_host += now_ms() - tg;
-    up(dpairs, hp, rows.size() * 16);
-    up(dlens, hl, rows.size() * 4);
-    up(dcol, hcc, (size_t)ent * 4);
-    k_scatter_rows<<<(unsigned)ceil_div((int64_t)rows.size() + 1, 256), 256, 0, s>>>(
-        dpairs, (int64_t)rows.size(), P.nptr, with_len ? rowlen : nullptr, dlens);
-    halo_rows += rows.size();
+    st.nrows = (int64_t)nr;
+    st.ent = ent;
+  };
+  auto upload_staged = [&](const Staged& st, const Pinned& S, bool with_len) -> int32_t* {
+    const size_t nr = (size_t)st.nrows;
+    D.used = fixed_used;
+    int64_t* dpairs = D.take<int64_t>(2 * nr + 2);
+    int32_t* dlens = D.take<int32_t>(nr + 1);
+    int32_t* dcol = D.take<int32_t>(st.ent + NCOL_PAD);
+    up(dpairs, S.p, nr * 16);
+    up(dlens, S.p + al((2 * nr + 2) * 8), nr * 4);
+    up(dcol, S.p + al((2 * nr + 2) * 8) + al((nr + 1) * 4), (size_t)st.ent * 4);
+    k_scatter_rows<<<(unsigned)ceil_div((int64_t)nr + 1, 256), 256, 0, s>>>(
+        dpairs, (int64_t)nr, P.nptr, with_len ? rowlen : nullptr, dlens);
+    halo_rows += nr;
     parts++;
     return dcol;
+  };
+  auto upload_rows = [&](bool with_len, int64_t) -> int32_t* {
+    Staged st;
+    Pinned& S = PS.stage[parts & 1];
+    const double tg = now_ms();
+    gather_rows(rows, S, st);
+    t_host += now_ms() - tg;
+    return upload_staged(st, S, with_len);
+  };
+  // Owner ranges from `next` (lo -> hi, filling its row list, throwing Fail
+  // on a budget error) counted by `count` (lo, hi) after their rows are on
+  // the device.  A host thread plans and gathers range k + 1 into the other
+  // pinned buffer while the device counts range k.
+  auto run_ranges = [&](int64_t start, bool with_len,
+                        const std::function<int64_t(int64_t, std::vector<RowPart>&)>& next,
+                        const std::function<void(int64_t, int64_t, int32_t*)>& count) {
+    if (start >= n) return;
+    std::mutex mu;
+    std::condition_variable cv;
+    Staged slot[2];
+    bool ready[2] = {false, false}, done = false;
+    double host_ms = 0;
+    std::thread producer([&] {
+      (void)hipSetDevice(c->device);
+      std::vector<RowPart> rr;
+      int64_t lo = start;
+      for (int k = 0;; k++) {
+        const int b = k & 1;
+        {
+          std::unique_lock<std::mutex> lk(mu);
+          cv.wait(lk, [&] { return !ready[b] || done; });
+          if (done) return;
+        }
+        Staged st;
+        const double t0 = now_ms();
+        try {
+          st.lo = lo;
+          st.hi = lo < n ? next(lo, rr) : n;
+          if (lo < n) gather_rows(rr, PS.stage[b], st);
+        } catch (const Fail& f) {
+          st.err = f.code;
+          st.msg = f.msg;
+        } catch (const std::exception& e) {
+          st.err = M4_ENOMEM;
+          st.msg = e.what();
+        }
+        const double t1 = now_ms();
+        std::lock_guard<std::mutex> lk(mu);
+        host_ms += t1 - t0;
+        slot[b] = st;
+        ready[b] = true;
+        cv.notify_all();
+        if (st.err != M4_OK || lo >= n) return;
+        lo = st.hi;
+      }
+    });
+    auto stop = [&] {
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        done = true;
+      }
+      cv.notify_all();
+      producer.join();
+    };
+    try {
+      for (int k = 0;; k++) {
+        const int b = k & 1;
+        Staged st;
+        {
+          std::unique_lock<std::mutex> lk(mu);
+          cv.wait(lk, [&] { return ready[b]; });
+          st = slot[b];
+        }
+        if (st.err != M4_OK) throw Fail(st.err, st.msg);
+        if (st.lo >= n) break;
+        int32_t* dcol = upload_staged(st, PS.stage[b], with_len);  // synchronous copies
+        {
+          std::lock_guard<std::mutex> lk(mu);
+          ready[b] = false;
+        }
+        cv.notify_all();
+        count(st.lo, st.hi, dcol);
+      }
+    } catch (...) {
+      stop();
+      t_host += host_ms;
+      throw;
+    }
+    stop();
+    t_host += host_ms;
   };
   auto tmp_arena = [&](size_t need) {
     Arena a;
@@ -576,21 +677,22 @@ int count_partitioned(m4_ctx* c, const m4_csr* g, const m4_opts* o, uint64_t out
   {
     const size_t cap_rows = D.cap > fixed_used + tri_tmp ? D.cap - fixed_used - tri_tmp : 0;
     TriPlanner plan(HR);
-    int64_t lo = 0;
-    while (lo < n) {
-      const double tp = now_ms();
-      size_t bytes = 0;
-      const int64_t hi = plan.next(lo, cap_rows, rows, bytes);
-      t_host += now_ms() - tp;
-      if (bytes > cap_rows) throw Fail(M4_ENOMEM, "device budget below one owner's halo");
-      P.ncol = upload_rows(false, 1);
-      P.own_lo = lo;
-      P.own_hi = hi;
-      Arena a = tmp_arena(tri_tmp);
-      tri_run(P, c->scal, tu, flags, o ? o->cache_rows : 0, a, s, c->num_cu, big, nullptr);
-      M4_HIP(hipStreamSynchronize(s));
-      lo = hi;
-    }
+    run_ranges(
+        0, false,
+        [&](int64_t lo, std::vector<RowPart>& rr) {
+          size_t bytes = 0;
+          const int64_t hi = plan.next(lo, cap_rows, rr, bytes);
+          if (bytes > cap_rows) throw Fail(M4_ENOMEM, "device budget below one owner's halo");
+          return hi;
+        },
+        [&](int64_t lo, int64_t hi, int32_t* dcol) {
+          P.ncol = dcol;
+          P.own_lo = lo;
+          P.own_hi = hi;
+          Arena a = tmp_arena(tri_tmp);
+          tri_run(P, c->scal, tu, flags, o ? o->cache_rows : 0, a, s, c->num_cu, big, nullptr);
+          M4_HIP(hipStreamSynchronize(s));
+        });
   }
 
   t_phase[1] = now_ms() - t_mark;
@@ -602,23 +704,24 @@ int count_partitioned(m4_ctx* c, const m4_csr* g, const m4_opts* o, uint64_t out
     const double tq = now_ms();
     C4Planner plan(HR, C.r1, nthreads);
     t_host += now_ms() - tq;
-    int64_t lo = C.r1;
-    while (lo < n) {
-      const double tp = now_ms();
-      size_t bytes = 0;
-      const int64_t hi = plan.next(lo, cap_rows, rows, bytes);
-      t_host += now_ms() - tp;
-      if (bytes > cap_rows) throw Fail(M4_ENOMEM, "device budget below one owner's halo");
-      P.ncol = upload_rows(true, 0);
-      P.row_len = rowlen;
-      P.own_lo = lo;
-      P.own_hi = hi;
-      Arena a = tmp_arena(c4_tmp);
-      c4_run(P, C, c->scal, tu, flags, a, s, c->num_cu, nullptr, big);
-      M4_HIP(hipStreamSynchronize(s));
-      P.row_len = nullptr;
-      lo = hi;
-    }
+    run_ranges(
+        C.r1, true,
+        [&](int64_t lo, std::vector<RowPart>& rr) {
+          size_t bytes = 0;
+          const int64_t hi = plan.next(lo, cap_rows, rr, bytes);
+          if (bytes > cap_rows) throw Fail(M4_ENOMEM, "device budget below one owner's halo");
+          return hi;
+        },
+        [&](int64_t lo, int64_t hi, int32_t* dcol) {
+          P.ncol = dcol;
+          P.row_len = rowlen;
+          P.own_lo = lo;
+          P.own_hi = hi;
+          Arena a = tmp_arena(c4_tmp);
+          c4_run(P, C, c->scal, tu, flags, a, s, c->num_cu, nullptr, big);
+          M4_HIP(hipStreamSynchronize(s));
+          P.row_len = nullptr;
+        });
   }
 
   t_phase[2] = now_ms() - t_mark;
