@@ -244,6 +244,11 @@ typedef struct {
                             device scratch holds (0 = 2^20, else 64..2^24);
                             an owner with more is binned in several rank
                             ranges                                           */
+  int32_t c4_bin_dense;  /* single graph: an owner that c4_bin_win would bin
+                            keeps the dense counter windows when its wedge
+                            bound is at least this many endpoints per window
+                            it needs (0 = never, else 64..2^20, default
+                            8192)                                             */
 } m4_tuning;
 
 int m4_get_tuning(const m4_ctx* ctx, m4_tuning* out);

@@ -113,9 +113,11 @@ __device__ __forceinline__ int64_t c4_windows(const int64_t* zb, int64_t r1, int
 // Beyond the one-pass table, an owner whose endpoints span at least bin_win
 // windows (and at most C4_BIN_KMAX) is binned: its endpoints are sorted into
 // per-window bins in device memory before counting, so a window costs only
-// its own endpoints instead of a pass over every lower neighbour's cursor.
+// its own endpoints instead of a pass over every lower neighbour's cursor;
+// unless they average at least bin_dense per window, where a dense window's
+// fixed cost is small beside its endpoints.
 struct C4Plan {
-  int light_max, med_max, med_win, bin_win;
+  int light_max, med_max, med_win, bin_win, bin_dense;
   const int64_t* zb;
   int64_t r1;
 };
@@ -123,7 +125,9 @@ __device__ __forceinline__ uint32_t c4_bucket(const C4Plan& pl, int64_t w, int64
   if (w <= pl.light_max) return CB_HASH;
   if (pl.med_max > 0 && w <= pl.med_max && w <= C4_MED_CAP) return CB_MED;
   const int64_t nwin = c4_windows(pl.zb, pl.r1, u);
-  if (pl.bin_win > 0 && nwin >= pl.bin_win && nwin <= C4_BIN_KMAX) return CB_BIN;
+  if (pl.bin_win > 0 && nwin >= pl.bin_win && nwin <= C4_BIN_KMAX &&
+      (pl.bin_dense <= 0 || w < (int64_t)pl.bin_dense * nwin))
+    return CB_BIN;
   if (pl.med_max <= 0) return CB_WIN;
   if (pl.med_win > 0 && w <= C4_MED_MAX && u - pl.r1 < C4_MED_SPAN &&
       16 * nwin >= (int64_t)pl.med_win * ((w + C4_MED_CAP - 1) / C4_MED_CAP))
@@ -1489,7 +1493,8 @@ Launch c4_plan(const Prep& P, const Classes& C, Scal* scal, const Tuning& tu, ui
   // zone bounds first: the planner needs every owner's window count
   int64_t* zbounds = start + C4_START_SLOTS;
   k_zone_bounds<<<1, 64, 0, s>>>(P.dr, n, zbounds);
-  C4Plan pl{tu.c4_light_max, tu.c4_med_max, tu.c4_med_win, tu.c4_bin_win, zbounds, C.r1};
+  C4Plan pl{tu.c4_light_max, tu.c4_med_max, tu.c4_med_win, tu.c4_bin_win, tu.c4_bin_dense,
+            zbounds, C.r1};
   // rows by degree: <= 64 with 8 lanes, <= 4096 with a wavefront, longer
   // rows with a workgroup
   const int64_t b64 = C.bound[4], b4096 = C.bound[7];

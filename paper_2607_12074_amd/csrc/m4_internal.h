@@ -125,6 +125,7 @@ struct Tuning {
   int c4_bin_win = 6;       // owners above the one-pass medium bound whose endpoints span at
                             // least this many counter windows are binned by window (0: never)
   int c4_bin_cap = 0;       // endpoints of a binning workgroup's scratch (0: 2^20)
+  int c4_bin_dense = 8192;  // endpoints per window from which an owner keeps dense windows (0: never)
   // weights of the anchor-selection objective, from stage times measured on
   // the MI355X over graphs of 10^2 to 10^7 edges: ns per wedge endpoint
   // bound, fixed us of the wedge stage (its plan kernels and host

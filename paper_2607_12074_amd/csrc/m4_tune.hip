@@ -39,6 +39,7 @@ void to_public(const Tuning& t, m4_tuning* out) {
   out->c4_med_win = t.c4_med_win;
   out->c4_bin_win = t.c4_bin_win;
   out->c4_bin_cap = t.c4_bin_cap;
+  out->c4_bin_dense = t.c4_bin_dense;
 }
 
 }  // namespace
@@ -57,7 +58,8 @@ extern "C" int m4_set_tuning(m4_ctx* ctx, const m4_tuning* t) {
       (t->hub_min != 0 && (t->hub_min < 4 || t->hub_min > 65536)) || t->c4_med_max < 0 ||
       t->c4_med_max > 3 * C4_MED_SLOTS / 4 || t->probe_w < 1 || t->probe_w > 256 ||
       t->c4_med_win < 0 || t->c4_med_win > 65536 || t->c4_bin_win < 0 || t->c4_bin_win > 65536 ||
-      (t->c4_bin_cap != 0 && (t->c4_bin_cap < 64 || t->c4_bin_cap > (1 << 24))))
+      (t->c4_bin_cap != 0 && (t->c4_bin_cap < 64 || t->c4_bin_cap > (1 << 24))) ||
+      (t->c4_bin_dense != 0 && (t->c4_bin_dense < 64 || t->c4_bin_dense > (1 << 20))))
     return set_error(ctx, M4_EINVAL, "tuning value out of range");
   ctx->tune.tri_wave_max = t->tri_wave_max;
   ctx->tune.c4_light_max = t->c4_light_max;
@@ -69,6 +71,7 @@ extern "C" int m4_set_tuning(m4_ctx* ctx, const m4_tuning* t) {
   ctx->tune.c4_med_win = t->c4_med_win;
   ctx->tune.c4_bin_win = t->c4_bin_win;
   ctx->tune.c4_bin_cap = t->c4_bin_cap;
+  ctx->tune.c4_bin_dense = t->c4_bin_dense;
   return M4_OK;
 }
 
@@ -161,16 +164,20 @@ extern "C" int m4_autotune(m4_ctx* ctx, const m4_csr* graph, const m4_batch* bat
           }
         }
       const int bin_wins[] = {0, 2, 4, 6, 8, 16};
+      const int bin_denses[] = {0, 4096, 8192, 16384};
       const Tuning after_med = best;
-      for (int bw : bin_wins) {
-        Tuning t = after_med;
-        t.c4_bin_win = bw;
-        const int rc = try_cfg(t);
-        if (rc != M4_OK) {
-          ctx->tune = start;
-          return rc;
+      for (int bw : bin_wins)
+        for (int bd : bin_denses) {
+          if (bw == 0 && bd != bin_denses[0]) continue;  // nothing binned
+          Tuning t = after_med;
+          t.c4_bin_win = bw;
+          t.c4_bin_dense = bd;
+          const int rc = try_cfg(t);
+          if (rc != M4_OK) {
+            ctx->tune = start;
+            return rc;
+          }
         }
-      }
       ctx->tune = start;
     }
     if (batch) {

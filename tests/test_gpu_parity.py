@@ -302,8 +302,9 @@ def test_binned_four_cycle_owners(ctx):
     # (c4_bin_win = 1), or only those spanning several windows, or none; the
     # binning scratch shrunk to 1000 endpoints (owners scattered in several
     # rank ranges) or to 64 (buckets alone beyond it, counted straight from
-    # the rows): the counts never change; the 300000-cycle graph spans two
-    # windows
+    # the rows); owners dense over their windows (c4_bin_dense) kept on the
+    # window kernel beside binned ones in the same count: the counts never
+    # change; the 300000-cycle graph spans two windows
     import paper_2607_12074_amd as m4
     cyc, bip = G.cycle(300000), G.complete_bipartite(50, 200)
     graphs = [gg.rmat(14, 10, 0.57, 0.19, 0.19, 5), gg.rmat(15, 16, 0.45, 0.22, 0.22, 6),
@@ -311,20 +312,30 @@ def test_binned_four_cycle_owners(ctx):
               G.disjoint_union(G.disjoint_union(cyc, bip), gg.ba(3000, 12, 7))]
     base = ctx.get_tuning()
     slot = m4.KERNELS.index("c4_bin")
-    binned = 0
+    wslot = m4.KERNELS.index("c4_window")
+    binned = split = 0
     try:
         for g in graphs:
             ref = oracle.closure(*g)
-            for bw, cap in ((1, 0), (1, 1000), (1, 64), (2, 0), (0, 0)):
-                ctx.set_tuning(c4_bin_win=bw, c4_bin_cap=cap)
+            # (bin_win, bin_cap, bin_dense, light_max, med_max); the last two
+            # bin owners from 256 endpoints so that a dense bound of 512 or
+            # 2048 per window splits them between the two kernels
+            for bw, cap, bd, lm, mm in ((1, 0, 0, 2048, 6144), (1, 1000, 0, 2048, 6144),
+                                        (1, 64, 0, 2048, 6144), (2, 0, 0, 2048, 6144),
+                                        (0, 0, 0, 2048, 6144), (1, 0, 512, 256, 0),
+                                        (1, 1000, 2048, 256, 0)):
+                ctx.set_tuning(c4_bin_win=bw, c4_bin_cap=cap, c4_bin_dense=bd, c4_light_max=lm,
+                               c4_med_max=mm)
                 got, st = ctx.count(*g, flags=m4.M4_BASIS_WEDGE, stats=True)
-                assert got == ref, (bw, cap)
+                assert got == ref, (bw, cap, bd, lm, mm)
                 if bw == 0:
                     assert st["k_rows"][slot] == 0
                 else:
                     binned += st["k_rows"][slot]
                     # every wedge endpoint of a binned owner is counted once
                     assert st["k_elems"][slot] <= st["wedges"]
+                    if bd and st["k_rows"][slot] and st["k_rows"][wslot]:
+                        split += 1
     finally:
         ctx.set_tuning(**base)
-    assert binned > 0
+    assert binned > 0 and split > 0
