@@ -226,7 +226,8 @@ typedef struct {
                             6144)                                             */
   int32_t probe_w;       /* single graph: a triangle row is probed in the hub
                             table when probe_w * (probes) < 3 * (elements a
-                            scan would read) (1..256, default 4)              */
+                            scan would read) (1..256, default 4), while the
+                            hub tables fit in the 256 MiB Infinity Cache     */
   int32_t c4_med_win;    /* single graph: an owner with wedge bound in
                             (12288, 65536] also uses the medium table, one
                             pass per rank range of at most 12288 endpoints,
@@ -249,6 +250,9 @@ typedef struct {
                             bound is at least this many endpoints per window
                             it needs (0 = never, else 64..2^20, default
                             8192)                                             */
+  int32_t probe_w_far;   /* single graph: probe_w when the hub tables exceed
+                            the Infinity Cache, so that a probe is a line
+                            read from HBM (1..256, default 16)                */
 } m4_tuning;
 
 int m4_get_tuning(const m4_ctx* ctx, m4_tuning* out);

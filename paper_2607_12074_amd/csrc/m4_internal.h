@@ -15,6 +15,8 @@
 namespace m4 {
 
 constexpr int WAVE = 64;
+// the MI355X's last-level cache (Infinity Cache) in front of HBM
+constexpr size_t kInfinityCacheBytes = size_t(256) << 20;
 
 // 128-bit unsigned accumulator in device memory, added to with two 64-bit
 // atomics (exact: the carry of the low word is derived from its own old value).
@@ -126,6 +128,7 @@ struct Tuning {
                             // least this many counter windows are binned by window (0: never)
   int c4_bin_cap = 0;       // endpoints of a binning workgroup's scratch (0: 2^20)
   int c4_bin_dense = 8192;  // endpoints per window from which an owner keeps dense windows (0: never)
+  int probe_w_far = 16;     // probe_w when the hub tables do not fit in the Infinity Cache
   // weights of the anchor-selection objective, from stage times measured on
   // the MI355X over graphs of 10^2 to 10^7 edges: ns per wedge endpoint
   // bound, fixed us of the wedge stage (its plan kernels and host

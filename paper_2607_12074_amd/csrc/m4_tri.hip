@@ -298,7 +298,10 @@ Launch tri_plan(const Prep& P, Scal* scal, const Tuning& tu, uint32_t flags, uin
       A.hoff = hoff;
       A.htab = htab;
       A.hub_min = tu.hub_min;
-      A.probe_w = tu.probe_w;
+      // a probe reads one line of a table: from the Infinity Cache while
+      // the tables fit there, else from HBM, where it weighs more against
+      // a scan's sequential reads
+      A.probe_w = hub_bytes > kInfinityCacheBytes ? tu.probe_w_far : tu.probe_w;
       if (kt) kt->end(M4_K_TRI_HUBS, ls);
     }
     auto run_lds = [&](auto kmax_tag, auto nt_tag, int bucket, int slot, int blocks_per_cu) {

@@ -40,6 +40,7 @@ void to_public(const Tuning& t, m4_tuning* out) {
   out->c4_bin_win = t.c4_bin_win;
   out->c4_bin_cap = t.c4_bin_cap;
   out->c4_bin_dense = t.c4_bin_dense;
+  out->probe_w_far = t.probe_w_far;
 }
 
 }  // namespace
@@ -59,7 +60,8 @@ extern "C" int m4_set_tuning(m4_ctx* ctx, const m4_tuning* t) {
       t->c4_med_max > 3 * C4_MED_SLOTS / 4 || t->probe_w < 1 || t->probe_w > 256 ||
       t->c4_med_win < 0 || t->c4_med_win > 65536 || t->c4_bin_win < 0 || t->c4_bin_win > 65536 ||
       (t->c4_bin_cap != 0 && (t->c4_bin_cap < 64 || t->c4_bin_cap > (1 << 24))) ||
-      (t->c4_bin_dense != 0 && (t->c4_bin_dense < 64 || t->c4_bin_dense > (1 << 20))))
+      (t->c4_bin_dense != 0 && (t->c4_bin_dense < 64 || t->c4_bin_dense > (1 << 20))) ||
+      t->probe_w_far < 1 || t->probe_w_far > 256)
     return set_error(ctx, M4_EINVAL, "tuning value out of range");
   ctx->tune.tri_wave_max = t->tri_wave_max;
   ctx->tune.c4_light_max = t->c4_light_max;
@@ -72,6 +74,7 @@ extern "C" int m4_set_tuning(m4_ctx* ctx, const m4_tuning* t) {
   ctx->tune.c4_bin_win = t->c4_bin_win;
   ctx->tune.c4_bin_cap = t->c4_bin_cap;
   ctx->tune.c4_bin_dense = t->c4_bin_dense;
+  ctx->tune.probe_w_far = t->probe_w_far;
   return M4_OK;
 }
 
@@ -141,7 +144,8 @@ extern "C" int m4_autotune(m4_ctx* ctx, const m4_csr* graph, const m4_batch* bat
           if (hm == 0 && pw != probe_ws[0]) continue;  // no tables: the weight is unused
           Tuning t = after_buckets;
           t.hub_min = hm;
-          t.probe_w = pw;
+          t.probe_w = pw;  // the sample graph decides which of the two weights applies
+          t.probe_w_far = pw;
           const int rc = try_cfg(t);
           if (rc != M4_OK) {
             ctx->tune = start;
