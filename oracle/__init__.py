@@ -16,6 +16,8 @@ Tiers (all plain C in ``m4ref.c``, reached through ctypes):
 * ``paper``   -- the closure equations of Section III-F applied as printed.
 * ``closure`` -- non-induced anchor counts (per-edge triangles, 4-cliques,
   4-cycles) plus the exact triangular inverse; also the CPU timing baseline.
+* ``orbits_brute`` / ``orbits_esu`` -- per-vertex graphlet orbit counts
+  (orbits 4..14) of the same induced 4-sets, from all subsets or ESU.
 """
 from __future__ import annotations
 
@@ -64,6 +66,9 @@ def _load():
         lib.m4ref_validate.restype = ctypes.c_int
         lib.m4ref_common.argtypes = [i64, p, p, i32, i32]
         lib.m4ref_common.restype = ctypes.c_int64
+        for f in ("m4ref_orbits_brute", "m4ref_orbits_esu"):
+            getattr(lib, f).argtypes = [i64, p, p, p]
+            getattr(lib, f).restype = ctypes.c_int
         lib.m4ref_threads.argtypes = [ctypes.c_int]
         lib.m4ref_threads.restype = ctypes.c_int
         _lib = lib
@@ -119,6 +124,30 @@ def closure(row_ptr, col, threads: int = 0, want_t: bool = False,
     if want_basis:
         res.append({k: int(v) for k, v in zip(BASIS, basis)})
     return res[0] if len(res) == 1 else tuple(res)
+
+
+ORBITS = tuple(range(4, 15))
+
+
+def _orbits(name, row_ptr, col):
+    n, rp, c = _csr(row_ptr, col)
+    orb = np.zeros((max(n, 1), 11), dtype=np.uint64)
+    rc = getattr(_load(), name)(n, rp.ctypes.data, c.ctypes.data, orb.ctypes.data)
+    if rc != 0:
+        raise OracleError(f"{name} failed with code {rc}")
+    return orb[:n]
+
+
+def orbits_brute(row_ptr, col):
+    """uint64[n, 11]: column o - 4 holds, per vertex, the induced 4-sets in
+    which it occupies graphlet orbit o (4..14), from every 4-vertex subset."""
+    return _orbits("m4ref_orbits_brute", row_ptr, col)
+
+
+def orbits_esu(row_ptr, col):
+    """The same per-vertex orbit counts from the ESU enumeration of the
+    connected 4-sets."""
+    return _orbits("m4ref_orbits_esu", row_ptr, col)
 
 
 def validate(row_ptr, col) -> bool:

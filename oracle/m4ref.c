@@ -82,6 +82,36 @@ static int classify_set(const int64_t* rp, const int32_t* col, const int32_t s[4
   return classify(deg[0], deg[1], deg[2], deg[3]);
 }
 
+/* Orbit of a vertex inside a connected induced 4-vertex graph of class c,
+ * from its degree d inside the set.  Graphlet orbits 4-14 in the numbering of
+ * Przulj's graphlet degree vectors (the one ORCA uses): path ends 4, path
+ * middles 5, claw leaves 6, claw centre 7, cycle 8, paw tail 9, paw triangle
+ * vertices of degree 2 10, paw vertex of degree 3 11, diamond vertices of
+ * degree 2 12 and of degree 3 13, clique 14.  In each class the degree inside
+ * the set tells the orbits apart. */
+static int orbit_of(int c, int d) {
+  switch (c) {
+    case PATH: return d == 1 ? 4 : 5;
+    case STAR: return d == 1 ? 6 : 7;
+    case CYCLE: return 8;
+    case PAW: return d == 1 ? 9 : (d == 2 ? 10 : 11);
+    case DIAMOND: return d == 2 ? 12 : 13;
+    case CLIQUE: return 14;
+    default: return -1;
+  }
+}
+
+/* Adds the induced 4-set s to the orbit counts of its four vertices. */
+static void add_orbits(const int64_t* rp, const int32_t* col, const int32_t s[4], uint64_t* orb) {
+  int deg[4] = {0, 0, 0, 0};
+  for (int i = 0; i < 4; i++)
+    for (int j = i + 1; j < 4; j++)
+      if (adjacent(rp, col, s[i], s[j])) { deg[i]++; deg[j]++; }
+  int c = classify(deg[0], deg[1], deg[2], deg[3]);
+  if (c < 0) return;
+  for (int i = 0; i < 4; i++) orb[(int64_t)s[i] * 11 + orbit_of(c, deg[i]) - 4]++;
+}
+
 int m4ref_threads(int threads) {
 #ifdef _OPENMP
   return threads > 0 ? threads : omp_get_max_threads();
@@ -151,6 +181,7 @@ typedef struct {
   int32_t sub[4];
   int32_t* ext[4]; /* extension buffer per depth */
   uint64_t cnt[6];
+  uint64_t* orb;   /* n x 11 orbit counts, or NULL */
 } esu_state;
 
 /* u is in the closed neighbourhood of the current subgraph sub[0..k) */
@@ -165,6 +196,7 @@ static void esu_extend(esu_state* s, int k, int64_t len) {
   if (k == 4) {
     int c = classify_set(s->rp, s->col, s->sub);
     if (c >= 0) s->cnt[c]++;
+    if (s->orb) add_orbits(s->rp, s->col, s->sub, s->orb);
     return;
   }
   int32_t* E = s->ext[k];
@@ -214,6 +246,53 @@ int m4ref_esu(int64_t n, const int64_t* rp, const int32_t* col, uint64_t out[6])
     esu_extend(&s, 1, len);
   }
   memcpy(out, s.cnt, sizeof(s.cnt));
+  for (int i = 0; i < 4; i++) free(s.ext[i]);
+  return 0;
+}
+
+/* ------------------------------------------ per-vertex orbit counts (O1, O2) */
+
+int m4ref_orbits_brute(int64_t n, const int64_t* rp, const int32_t* col, uint64_t* orb) {
+  if (n < 0) return 1;
+  if (n > 1024) return 7;
+  memset(orb, 0, (size_t)n * 11 * sizeof(uint64_t));
+  for (int32_t a = 0; a < n; a++)
+    for (int32_t b = a + 1; b < n; b++)
+      for (int32_t c = b + 1; c < n; c++)
+        for (int32_t d = c + 1; d < n; d++) {
+          const int32_t set[4] = {a, b, c, d};
+          add_orbits(rp, col, set, orb);
+        }
+  return 0;
+}
+
+int m4ref_orbits_esu(int64_t n, const int64_t* rp, const int32_t* col, uint64_t* orb) {
+  if (n < 0) return 1;
+  memset(orb, 0, (size_t)n * 11 * sizeof(uint64_t));
+  int64_t dmax = 0;
+  for (int64_t v = 0; v < n; v++)
+    if (rp[v + 1] - rp[v] > dmax) dmax = rp[v + 1] - rp[v];
+  size_t cap = (size_t)(4 * dmax + 8);
+  esu_state s;
+  memset(&s, 0, sizeof(s));
+  s.rp = rp;
+  s.col = col;
+  s.orb = orb;
+  for (int i = 0; i < 4; i++) {
+    s.ext[i] = (int32_t*)malloc(cap * sizeof(int32_t));
+    if (!s.ext[i]) {
+      for (int j = 0; j < i; j++) free(s.ext[j]);
+      return 4;
+    }
+  }
+  for (int64_t v = 0; v < n; v++) {
+    s.root = (int32_t)v;
+    s.sub[0] = (int32_t)v;
+    int64_t len = 0;
+    for (int64_t p = rp[v]; p < rp[v + 1]; p++)
+      if (col[p] > v) s.ext[1][len++] = col[p];
+    esu_extend(&s, 1, len);
+  }
   for (int i = 0; i < 4; i++) free(s.ext[i]);
   return 0;
 }

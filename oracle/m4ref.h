@@ -59,6 +59,18 @@ int m4ref_closure(int64_t n, const int64_t* row_ptr, const int32_t* col,
                   int threads, uint64_t out[6], uint32_t* t_csr,
                   uint64_t basis[8]);
 
+/* Per-vertex graphlet orbit counts of the connected 4-vertex graphs: orb is
+ * uint64[n][11], entry [v][o - 4] the number of induced 4-sets S containing v
+ * in which v occupies orbit o (Przulj's numbering, as used by ORCA, which the
+ * paper names in its related work, Section V): 4/5 path end/middle, 6/7 claw
+ * leaf/centre, 8 cycle, 9/10/11 paw tail / degree-2 / degree-3, 12/13
+ * diamond degree-2 / degree-3, 14 clique.  The orbit of v follows from the
+ * class of G[S] and v's degree inside S.
+ *   m4ref_orbits_brute: every 4-vertex subset (n <= 1024);
+ *   m4ref_orbits_esu:   every connected 4-set once by ESU. */
+int m4ref_orbits_brute(int64_t n, const int64_t* row_ptr, const int32_t* col, uint64_t* orb);
+int m4ref_orbits_esu(int64_t n, const int64_t* row_ptr, const int32_t* col, uint64_t* orb);
+
 /* |N(u) intersect N(v)| by a plain merge of the two sorted rows. */
 int64_t m4ref_common(int64_t n, const int64_t* row_ptr, const int32_t* col,
                      int32_t u, int32_t v);
