@@ -196,6 +196,24 @@ int m4_count_motifs4_ex(m4_ctx* ctx, const m4_csr* g, const m4_opts* opts,
 int m4_edge_triangles(m4_ctx* ctx, const m4_csr* g, const m4_opts* opts,
                       uint32_t* t_out);
 
+/* Per-vertex graphlet orbit counts of the connected 4-vertex graphs: for every
+ * vertex v and orbit o in 4..14 (Przulj's numbering, the one of ORCA, whose
+ * orbit equations the paper names in its related work, Section V), the number
+ * of induced 4-sets containing v in which v sits at o -- 4/5 path end/middle,
+ * 6/7 claw leaf/centre, 8 cycle, 9/10/11 paw tail / degree-2 / degree-3
+ * vertex, 12/13 diamond degree-2 / degree-3 vertex, 14 clique.  The same
+ * closure idea as the count (Section III-F) applied per vertex: non-induced
+ * local statistics from the triangle anchor (t_e, the induced subgraph on
+ * N+(u)) and the wedge 4-cycle anchor, then the per-vertex inverse.
+ *   orbits  uint64[n][11], row v = the caller's vertex v, column o - 4;
+ *           device memory when g->on_device, else host; caller-owned.
+ * Only M4_VALIDATE of opts->flags is used; a device budget is not supported
+ * (M4_EINVAL).  M4_EOVERFLOW when a count is >= 2^64, M4_EINTERNAL when the
+ * per-vertex inverse is inconsistent.  The graph and 8n words of statistics
+ * stay resident, plus the 4-cycle counters (4n bytes per workgroup, at most
+ * 8 GiB in all). */
+int m4_count_orbits4(m4_ctx* ctx, const m4_csr* g, const m4_opts* opts, uint64_t* orbits);
+
 /* --------------------------------------------------------------- tuning --
  * Degree-bucket and tile thresholds of a context.  They move owners between
  * kernels and never change a count.  m4_autotune times every candidate on

@@ -129,6 +129,7 @@ def lib():
         L.m4_count_motifs4_ex.argtypes = [p, ctypes.POINTER(Csr), ctypes.POINTER(Opts), p,
                                           ctypes.POINTER(Stats)]
         L.m4_edge_triangles.argtypes = [p, ctypes.POINTER(Csr), ctypes.POINTER(Opts), p]
+        L.m4_count_orbits4.argtypes = [p, ctypes.POINTER(Csr), ctypes.POINTER(Opts), p]
         L.m4_count_batch.argtypes = [p, ctypes.POINTER(Batch), ctypes.POINTER(Opts), p,
                                      ctypes.POINTER(Stats)]
         L.m4_get_tuning.argtypes = [p, ctypes.POINTER(Tuning)]
@@ -260,6 +261,24 @@ class Context:
             ptr = t.ctypes.data
         self._check(lib().m4_edge_triangles(self.h, ctypes.byref(g), ctypes.byref(o), ptr))
         return t[: g.nnz]
+
+    def orbits(self, row_ptr, col, *, flags=0, budget=0, stream=None):
+        """Per-vertex graphlet orbit counts (orbits 4..14, column o - 4): numpy
+        uint64 (n, 11) for host inputs, a torch int64 (n, 11) tensor holding
+        uint64 bits for device inputs.  A device budget is rejected."""
+        keep = _Keep()
+        g = make_csr(row_ptr, col, keep)
+        o = make_opts(flags, budget, 0, self._stream_for(row_ptr, stream))
+        n = g.n
+        if g.on_device:
+            import torch
+            out = torch.empty((max(n, 1), 11), dtype=torch.int64, device=row_ptr.device)
+            ptr = out.data_ptr()
+        else:
+            out = np.zeros((max(n, 1), 11), dtype=np.uint64)
+            ptr = out.ctypes.data
+        self._check(lib().m4_count_orbits4(self.h, ctypes.byref(g), ctypes.byref(o), ptr))
+        return out[:n]
 
     def get_tuning(self) -> dict:
         t = Tuning()

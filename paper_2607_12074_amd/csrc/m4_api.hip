@@ -498,6 +498,92 @@ extern "C" int m4_edge_triangles(m4_ctx* ctx, const m4_csr* g, const m4_opts* o,
   M4_GUARD_END
 }
 
+extern "C" int m4_count_orbits4(m4_ctx* ctx, const m4_csr* g, const m4_opts* o,
+                                uint64_t* orbits) {
+  if (!ctx || !orbits) return M4_EINVAL;
+  int rc = check_csr_args(g);
+  if (rc) return set_error(ctx, rc, "bad CSR arguments");
+  if (o && o->device_budget_bytes > 0)
+    return set_error(ctx, M4_EINVAL, "orbit counts need the whole graph resident (no budget)");
+  M4_GUARD_BEGIN
+  M4_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = (o && o->hip_stream) ? (hipStream_t)o->hip_stream : ctx->stream;
+  const int64_t n = g->n;
+  if (n == 0) return M4_OK;
+  const size_t out_bytes = (size_t)n * 11 * sizeof(uint64_t);
+  if (g->nnz == 0) {
+    if (g->on_device) {
+      fill_u32(orbits, 0, out_bytes / 4, s);
+      M4_HIP(hipStreamSynchronize(s));
+    } else {
+      memset(orbits, 0, out_bytes);
+    }
+    return M4_OK;
+  }
+  const int64_t* rp;
+  const int32_t* col;
+  stage_input(ctx, g, s, &rp, &col, nullptr);
+  if (!g->on_device) {
+    int64_t last = 0;
+    M4_HIP(hipMemcpyAsync(&last, rp + n, 8, hipMemcpyDeviceToHost, s));
+    M4_HIP(hipStreamSynchronize(s));
+    if (last != g->nnz) return set_error(ctx, M4_ERANGE, "row_ptr[n] != nnz");
+  }
+  const uint32_t flags = o ? (o->flags & M4_VALIDATE) : 0;
+  const Tuning tu = tuning_for(ctx, o);
+  ctx->prep.ensure(prep_bytes(n, g->nnz), s);
+  Prep P = carve_prep(ctx->prep.ptr, n, g->nnz);
+  fill_u32(ctx->scal, 0, sizeof(Scal) / 4, s);
+  fill_u32(P.t, 0, (size_t)(g->nnz / 2), s);
+  ctx->tmp.ensure(stage_tmp_bytes(n, g->nnz, 1, ctx->num_cu), s);
+  Arena a;
+  a.base = ctx->tmp.ptr;
+  a.cap = ctx->tmp.cap;
+  Classes C{};
+  build_prep(rp, col, n, g->nnz, (flags & M4_VALIDATE) != 0, P, C, ctx->scal, ctx->scal_host, a,
+             s);
+  a.used = 0;
+  auto big = [ctx, s](size_t bytes) -> char* {
+    ctx->big.ensure(bytes, s);
+    return ctx->big.ptr;
+  };
+  tri_run(P, ctx->scal, tu, flags, 0, a, s, ctx->num_cu, big, nullptr);
+  // statistics (8 n words) and the bitmap slices of out-degrees above the
+  // LDS bound in big2; the 4-cycle counters (4 n bytes per workgroup, at
+  // most 8 GiB, at most 4 workgroups per CU) in big
+  const int kmax = local_dplus_max(P, ctx->scal, s);
+  const size_t arr_bytes = align256((size_t)n * 8 * 8);
+  int gblocks = 0;
+  size_t g_bytes = 0;
+  if (kmax > 512) {
+    const size_t per = local_glob_stride_words(kmax) * 8;
+    gblocks = (int)std::max<size_t>(1, std::min<size_t>((size_t(1) << 30) / per, 64));
+    g_bytes = (size_t)gblocks * per;
+  }
+  ctx->big2.ensure(arr_bytes + g_bytes, s);
+  const int cblocks = (int)std::max<int64_t>(
+      1, std::min<int64_t>((int64_t(8) << 30) / ((int64_t)n * 4), 4 * (int64_t)ctx->num_cu));
+  ctx->big.ensure((size_t)cblocks * (size_t)n * 4, s);
+  unsigned long long* dst = reinterpret_cast<unsigned long long*>(orbits);
+  if (!g->on_device) {
+    ctx->tout.ensure(out_bytes, s);
+    dst = reinterpret_cast<unsigned long long*>(ctx->tout.ptr);
+  }
+  local_orbits(P, C, ctx->scal, reinterpret_cast<unsigned long long*>(ctx->big2.ptr),
+               reinterpret_cast<uint32_t*>(ctx->big.ptr), cblocks,
+               gblocks ? reinterpret_cast<unsigned long long*>(ctx->big2.ptr + arr_bytes) : nullptr,
+               gblocks, kmax, dst, ctx->num_cu, s);
+  if (!g->on_device) M4_HIP(hipMemcpyAsync(orbits, dst, out_bytes, hipMemcpyDeviceToHost, s));
+  M4_HIP(hipMemcpyAsync(ctx->scal_host, ctx->scal, sizeof(Scal), hipMemcpyDeviceToHost, s));
+  M4_HIP(hipStreamSynchronize(s));
+  const Scal& h = *ctx->scal_host;
+  if (h.err & 8) return set_error(ctx, M4_EINTERNAL, "per-vertex orbit inverse went negative");
+  if (h.err) return scal_error(ctx, h.err);
+  if (h.status == 3) return set_error(ctx, M4_EOVERFLOW, "an orbit count is >= 2^64");
+  return M4_OK;
+  M4_GUARD_END
+}
+
 static std::once_flag g_default_once;
 static m4_ctx* g_default = nullptr;
 static int g_default_rc = M4_OK;
