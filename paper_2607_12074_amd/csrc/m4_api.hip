@@ -549,8 +549,8 @@ extern "C" int m4_count_orbits4(m4_ctx* ctx, const m4_csr* g, const m4_opts* o,
   };
   tri_run(P, ctx->scal, tu, flags, 0, a, s, ctx->num_cu, big, nullptr);
   // statistics (8 n words) and the bitmap slices of out-degrees above the
-  // LDS bound in big2; the 4-cycle counters (4 n bytes per workgroup, at
-  // most 8 GiB, at most 4 workgroups per CU) in big
+  // LDS bound in big2; the 4-cycle counters (4 n bytes per workgroup, 8 n
+  // from degree 2^16, at most 8 GiB, at most 4 workgroups per CU) in big
   const int kmax = local_dplus_max(P, ctx->scal, s);
   const size_t arr_bytes = align256((size_t)n * 8 * 8);
   int gblocks = 0;
@@ -561,16 +561,18 @@ extern "C" int m4_count_orbits4(m4_ctx* ctx, const m4_csr* g, const m4_opts* o,
     g_bytes = (size_t)gblocks * per;
   }
   ctx->big2.ensure(arr_bytes + g_bytes, s);
+  const bool wide = C.dmax >= 65536;
+  const int64_t cword = wide ? 8 : 4;
   const int cblocks = (int)std::max<int64_t>(
-      1, std::min<int64_t>((int64_t(8) << 30) / ((int64_t)n * 4), 4 * (int64_t)ctx->num_cu));
-  ctx->big.ensure((size_t)cblocks * (size_t)n * 4, s);
+      1, std::min<int64_t>((int64_t(8) << 30) / ((int64_t)n * cword), 4 * (int64_t)ctx->num_cu));
+  ctx->big.ensure((size_t)cblocks * (size_t)n * (size_t)cword, s);
   unsigned long long* dst = reinterpret_cast<unsigned long long*>(orbits);
   if (!g->on_device) {
     ctx->tout.ensure(out_bytes, s);
     dst = reinterpret_cast<unsigned long long*>(ctx->tout.ptr);
   }
   local_orbits(P, C, ctx->scal, reinterpret_cast<unsigned long long*>(ctx->big2.ptr),
-               reinterpret_cast<uint32_t*>(ctx->big.ptr), cblocks,
+               ctx->big.ptr, wide, cblocks,
                gblocks ? reinterpret_cast<unsigned long long*>(ctx->big2.ptr + arr_bytes) : nullptr,
                gblocks, kmax, dst, ctx->num_cu, s);
   if (!g->on_device) M4_HIP(hipMemcpyAsync(orbits, dst, out_bytes, hipMemcpyDeviceToHost, s));

@@ -240,8 +240,8 @@ inline void tri_run(const Prep& P, Scal* scal, const Tuning& tu, uint32_t flags,
 
 // m4_local.hip: per-vertex orbit counts of a prepared graph (t complete)
 void local_orbits(const Prep& P, const Classes& C, Scal* scal, unsigned long long* arrays,
-                  uint32_t* cscr, int cblocks, unsigned long long* gscr, int gblocks, int kmax,
-                  unsigned long long* out, int num_cu, hipStream_t s);
+                  void* cscr, bool wide, int cblocks, unsigned long long* gscr, int gblocks,
+                  int kmax, unsigned long long* out, int num_cu, hipStream_t s);
 size_t local_glob_stride_words(int kmax);
 int local_dplus_max(const Prep& P, Scal* scal, hipStream_t s);
 

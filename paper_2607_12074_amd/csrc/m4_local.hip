@@ -177,6 +177,19 @@ __device__ __forceinline__ unsigned long long ld_word(const unsigned long long* 
   return *p;
 }
 
+// A wavefront's bit list: in LDS, or in device scratch (written and read by
+// the same wavefront; the device-scope loads skip the L1).
+template <bool GLOB>
+__device__ __forceinline__ int ld_list(const int32_t* p) {
+  if (GLOB) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return *p;
+}
+template <bool GLOB>
+__device__ __forceinline__ void wave_list_sync() {
+  if (GLOB) __threadfence();
+  wave_sync();
+}
+
 // Triangle owners u (their lowest vertex) with out-degree k in [k_lo, k_hi],
 // ranks from r_start up, LOC_TRI_CHUNK per grab.  Row i of the bitmap holds
 // bit j when a[j] is in N+(a[i]), a = N+(u) (so j > i: rows are the
@@ -190,11 +203,13 @@ __global__ __launch_bounds__(LOC_NT) void k_loc_cliques(LocIn in, LocArrays L, i
   __shared__ unsigned long long s_bits[GLOB ? 1 : LOC_K_LDS * LOC_W_LDS];
   __shared__ unsigned long long s_c12[GLOB ? 1 : LOC_K_LDS], s_c14[GLOB ? 1 : LOC_K_LDS];
   __shared__ int32_t s_a[GLOB ? 1 : LOC_K_LDS];
+  __shared__ int32_t s_list[GLOB ? 1 : LOC_NW * LOC_K_LDS];
   __shared__ int64_t s_g;
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
   unsigned long long* bits;
   unsigned long long *c12, *c14;
-  int32_t* a;
+  int32_t *a, *list;
+  int64_t list_cap;
   if (GLOB) {
     unsigned long long* base = gscr + (int64_t)blockIdx.x * stride;
     const int64_t W = (k_hi + 63) / 64;
@@ -202,11 +217,15 @@ __global__ __launch_bounds__(LOC_NT) void k_loc_cliques(LocIn in, LocArrays L, i
     c12 = base + (int64_t)k_hi * W;
     c14 = c12 + k_hi;
     a = reinterpret_cast<int32_t*>(c14 + k_hi);
+    list = a + k_hi;
+    list_cap = k_hi;
   } else {
     bits = s_bits;
     c12 = s_c12;
     c14 = s_c14;
     a = s_a;
+    list = s_list;
+    list_cap = LOC_K_LDS;
   }
   for (;;) {
     if (tid == 0) s_g = (int64_t)atomicAdd(work, 1u) * LOC_TRI_CHUNK + r_start;
@@ -257,35 +276,55 @@ __global__ __launch_bounds__(LOC_NT) void k_loc_cliques(LocIn in, LocArrays L, i
       }
       __syncthreads();
       // 4-cliques u < a[i] < a[j] < a[l]: bits l of row i AND row j, for
-      // every bit j of row i
+      // every bit j of row i.  A wavefront lists row i's bits (each lane
+      // its words' bits at its offset of a wave prefix), then its lanes
+      // take the listed j's.
+      int32_t* lst = list + (int64_t)wv * list_cap;
       for (int i = wv; i < k; i += LOC_NW) {
         const unsigned long long* ri = bits + (int64_t)i * W;
-        unsigned long long ci = 0;
+        int mine = 0;
+        for (int w = lane; w < W; w += WAVE) mine += __popcll(ld_word<GLOB>(ri + w));
+        int incl = mine;
+#pragma unroll
+        for (int o = 1; o < WAVE; o <<= 1) {
+          const int y = __shfl_up(incl, o, WAVE);
+          if (lane >= o) incl += y;
+        }
+        const int total = __shfl(incl, WAVE - 1, WAVE);
+        int q = incl - mine;
         for (int w = lane; w < W; w += WAVE) {
           unsigned long long m = ld_word<GLOB>(ri + w);
           while (m) {
-            const int jx = w * 64 + __builtin_ctzll(m);
+            lst[q++] = w * 64 + __builtin_ctzll(m);
             m &= m - 1;
-            const unsigned long long* rj = bits + (int64_t)jx * W;
-            unsigned long long cj = 0;
-            for (int y = jx >> 6; y < W; y++) {
-              unsigned long long andw = ld_word<GLOB>(ri + y) & ld_word<GLOB>(rj + y);
-              cj += (unsigned long long)__popcll(andw);
-              while (andw) {
-                const int lx = y * 64 + __builtin_ctzll(andw);
-                andw &= andw - 1;
-                atomicAdd(&c14[lx], 1ull);
-              }
+          }
+        }
+        wave_list_sync<GLOB>();
+        unsigned long long ci = 0;
+        for (int e = lane; e < total; e += WAVE) {
+          const int jx = ld_list<GLOB>(lst + e);
+          const unsigned long long* rj = bits + (int64_t)jx * W;
+          unsigned long long cj = 0;
+          for (int y = jx >> 6; y < W; y++) {
+            unsigned long long andw = ld_word<GLOB>(ri + y) & ld_word<GLOB>(rj + y);
+            cj += (unsigned long long)__popcll(andw);
+            while (andw) {
+              const int lx = y * 64 + __builtin_ctzll(andw);
+              andw &= andw - 1;
+              atomicAdd(&c14[lx], 1ull);
             }
-            if (cj) {
-              ci += cj;
-              cu14 += cj;
-              atomicAdd(&c14[jx], cj);
-            }
+          }
+          if (cj) {
+            ci += cj;
+            cu14 += cj;
+            atomicAdd(&c14[jx], cj);
           }
         }
         ci = group_sum<WAVE>(ci);
         if (lane == 0 && ci) atomicAdd(&c14[i], ci);
+        // the list is rewritten for the next row only after every lane
+        // has read it
+        wave_list_sync<GLOB>();
       }
       __syncthreads();
       for (int i = tid; i < k; i += LOC_NT) {
@@ -300,13 +339,20 @@ __global__ __launch_bounds__(LOC_NT) void k_loc_cliques(LocIn in, LocArrays L, i
 }
 
 // 4-cycle owners u (their highest vertex), heaviest first.  Each block keeps
-// n wedge counters in device scratch, all zero between owners.
+// n wedge counters of type CT in device scratch, all zero between owners:
+// the low half counts a wedge endpoint's wedges in the first pass, the high
+// half its visits in the second, whose last visitor credits the endpoint and
+// clears the counter.  An endpoint's wedges come from distinct lower
+// neighbours of u, so 16-bit halves hold them while degrees stay below 2^16.
+template <typename CT>
 __global__ __launch_bounds__(LOC_NT) void k_loc_cycles(LocIn in, int64_t r1, LocArrays L,
-                                                       uint32_t* cscr, unsigned int* work) {
+                                                       CT* cscr, unsigned int* work) {
+  constexpr int HALF = (int)sizeof(CT) * 4;
+  constexpr CT LOC_LOW = (CT(1) << HALF) - 1;
   __shared__ int64_t s_g;
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
   const int64_t n = in.n;
-  uint32_t* c = cscr + (int64_t)blockIdx.x * n;
+  CT* c = cscr + (int64_t)blockIdx.x * n;
   for (;;) {
     if (tid == 0) s_g = (int64_t)atomicAdd(work, 1u);
     __syncthreads();
@@ -333,35 +379,30 @@ __global__ __launch_bounds__(LOC_NT) void k_loc_cycles(LocIn in, int64_t r1, Loc
         const int32_t v = in.ncol[ub + i];
         const int64_t vb = in.nptr[v];
         const int64_t pe = lower_index(in.ncol, vb, vb + in.dr[v], (int32_t)u);
-        for (int64_t p = vb + lane; p < pe; p += WAVE) pairs += atomicAdd(&c[in.ncol[p]], 1u);
+        for (int64_t p = vb + lane; p < pe; p += WAVE)
+          pairs += (unsigned long long)(atomicAdd(&c[in.ncol[p]], CT(1)) & LOC_LOW);
       }
       __syncthreads();
       // pass 2: a middle vertex v shares each of its wedges with c[w] - 1
-      // others (device-scope loads: the counters were written by atomics)
+      // others; the c[w]-th visit of w gives w its C(c[w], 2) cycles with
+      // u and clears the counter
       for (int i = wv; i < nl; i += LOC_NW) {
         const int32_t v = in.ncol[ub + i];
         const int64_t vb = in.nptr[v];
         const int64_t pe = lower_index(in.ncol, vb, vb + in.dr[v], (int32_t)u);
         unsigned long long acc = 0;
-        for (int64_t p = vb + lane; p < pe; p += WAVE)
-          acc += (unsigned long long)__hip_atomic_load(&c[in.ncol[p]], __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_AGENT) -
-                 1;
-        acc = group_sum<WAVE>(acc);
-        if (lane == 0 && acc) atomicAdd(&L.N8[v], acc);
-      }
-      __syncthreads();
-      // pass 3: the opposite corner w gains C(c[w], 2), once, as the
-      // counter is cleared
-      for (int i = wv; i < nl; i += LOC_NW) {
-        const int32_t v = in.ncol[ub + i];
-        const int64_t vb = in.nptr[v];
-        const int64_t pe = lower_index(in.ncol, vb, vb + in.dr[v], (int32_t)u);
         for (int64_t p = vb + lane; p < pe; p += WAVE) {
           const int32_t w = in.ncol[p];
-          const unsigned long long x = atomicExch(&c[w], 0u);
-          if (x >= 2) atomicAdd(&L.N8[w], x * (x - 1) / 2);
+          const CT old = atomicAdd(&c[w], CT(1) << HALF);
+          const unsigned long long k = (unsigned long long)(old & LOC_LOW);
+          acc += k - 1;
+          if ((unsigned long long)(old >> HALF) == k - 1) {
+            atomicExch(&c[w], CT(0));
+            if (k >= 2) atomicAdd(&L.N8[w], k * (k - 1) / 2);
+          }
         }
+        acc = group_sum<WAVE>(acc);
+        if (lane == 0 && acc) atomicAdd(&L.N8[v], acc);
       }
       block_add_u64<LOC_NT>(&L.N8[u], pairs);
     }
@@ -439,11 +480,11 @@ __global__ void k_loc_dplus_max(const int32_t* __restrict__ dplus, int64_t n,
 
 // Orbit counts of the prepared graph P (t complete) into out (uint64[n][11],
 // device memory, caller's vertex ids).  arrays: 8 n words; cscr: the 4-cycle
-// counters, cblocks x n words; gscr: the bitmap slices of out-degrees above
+// counters, cblocks x n of 32 bits (64 when wide: degrees of 2^16 and more); gscr: the bitmap slices of out-degrees above
 // the LDS bound (kmax > LOC_K_LDS), gblocks slices.
 void local_orbits(const Prep& P, const Classes& C, Scal* scal, unsigned long long* arrays,
-                  uint32_t* cscr, int cblocks, unsigned long long* gscr, int gblocks, int kmax,
-                  unsigned long long* out, int num_cu, hipStream_t s) {
+                  void* cscr, bool wide, int cblocks, unsigned long long* gscr, int gblocks,
+                  int kmax, unsigned long long* out, int num_cu, hipStream_t s) {
   const int64_t n = P.n;
   LocIn in{P.nptr, P.optr, P.ncol, P.dr, P.dlo, P.dplus, P.t, P.perm, n};
   LocArrays L{arrays,         arrays + n,     arrays + 2 * n, arrays + 3 * n,
@@ -469,8 +510,13 @@ void local_orbits(const Prep& P, const Classes& C, Scal* scal, unsigned long lon
         &scal->work[1], scal);
   }
   if (cblocks > 0) {
-    fill_u32(cscr, 0, (size_t)cblocks * (size_t)n, s);
-    k_loc_cycles<<<(unsigned)cblocks, LOC_NT, 0, s>>>(in, C.r1, L, cscr, &scal->work[2]);
+    fill_u32(cscr, 0, (size_t)cblocks * (size_t)n * (wide ? 2 : 1), s);
+    if (wide)
+      k_loc_cycles<unsigned long long><<<(unsigned)cblocks, LOC_NT, 0, s>>>(
+          in, C.r1, L, reinterpret_cast<unsigned long long*>(cscr), &scal->work[2]);
+    else
+      k_loc_cycles<unsigned int><<<(unsigned)cblocks, LOC_NT, 0, s>>>(
+          in, C.r1, L, reinterpret_cast<unsigned int*>(cscr), &scal->work[2]);
   }
   if (b64 > 0) k_loc_final<8><<<grid_for(b64, 8), 256, 0, s>>>(in, 0, b64, L, out, scal);
   if (n > b64) k_loc_final<64><<<grid_for(n - b64, 64), 256, 0, s>>>(in, b64, n, L, out, scal);
@@ -487,9 +533,11 @@ int local_dplus_max(const Prep& P, Scal* scal, hipStream_t s) {
   return (int)k;
 }
 
+// per block: the bitmap (kmax rows of ceil(kmax / 64) words), the two
+// credit arrays, a (kmax int32) and one bit list per wavefront (kmax int32)
 size_t local_glob_stride_words(int kmax) {
   const int64_t W = (kmax + 63) / 64;
-  return (size_t)((int64_t)kmax * W + 2 * (int64_t)kmax + (kmax + 1) / 2);
+  return (size_t)((int64_t)kmax * W + 2 * (int64_t)kmax + ((int64_t)kmax * (1 + LOC_NW) + 1) / 2);
 }
 
 }  // namespace m4

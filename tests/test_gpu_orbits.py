@@ -72,6 +72,14 @@ def test_out_degree_beyond_the_lds_bitmap(ctx):
     assert (got[600:] == oracle.orbits_esu(*small)).all()
 
 
+def test_degree_beyond_16_bit_counters(ctx):
+    # K_{2,70000}: the top vertex's lower neighbours all reach the other
+    # side-A vertex, 70000 wedges on one endpoint (wide 4-cycle counters)
+    from tests.test_oracle_orbits import cf_bipartite
+    got = ctx.orbits(*G.complete_bipartite(2, 70000))
+    assert (got == cf_bipartite(2, 70000)).all()
+
+
 def test_device_inputs_and_edge_cases(ctx):
     import torch
     import paper_2607_12074_amd as m4
