@@ -15,8 +15,9 @@ the dominant kernel (algorithmic bytes per launch over its HIP-event duration,
 taken from further steps that run the stages one after the other so that a
 kernel's events time it alone), the same graph under a 4 GB device budget
 (halo partitions streamed from pinned host memory), the CPU oracle timed on
-this host's cores, and secondary blocks: the social R-MAT scale-20 graph, the
-batched launch of 4096 uneven graphs and the serving loop.
+this host's cores, and secondary blocks: the per-vertex orbit counts of the
+graph, the social R-MAT scale-20 graph (with its orbit counts), the batched
+launch of 4096 uneven graphs and the serving loop.
 """
 from __future__ import annotations
 
@@ -453,6 +454,32 @@ def run_budget_leg(ctx, rp, col, budget_gb, resident_counts):
                     "uploads are inside the time"}
 
 
+def run_orbits_leg(ctx, rp, col, counts, reps: int):
+    """Per-vertex orbit counts (orbits 4..14) of the resident graph: one
+    untimed call, then reps timed calls; the orbit totals must give the six
+    counts of the resident count."""
+    import numpy as np
+    import torch
+    rpd, cold = torch.from_numpy(rp).cuda(), torch.from_numpy(col).cuda()
+    out = ctx.orbits(rpd, cold)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        out = ctx.orbits(rpd, cold)
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t0) * 1e3)
+    c = out.sum(dim=0).cpu().numpy().view(np.uint64)
+    tot = (int(c[3]), int(c[1]) // 2, int(c[7]), int(c[4]) // 4, int(c[9]) // 2, int(c[10]) // 4)
+    m = len(col) // 2
+    ms = float(np.median(ts))
+    del rpd, cold, out
+    torch.cuda.empty_cache()
+    return {"ms": ms, "ms_min": min(ts), "reps": reps, "edges_per_s": m / (ms * 1e-3),
+            "totals_equal_counts": tot == tuple(counts),
+            "note": "uint64[n][11] per-vertex orbit counts, CSR resident, output on the device"}
+
+
 def cpu_model() -> str:
     try:
         for line in open("/proc/cpuinfo"):
@@ -520,6 +547,8 @@ def main():
     ap.add_argument("--no-social", action="store_true",
                     help="skip the secondary social R-MAT scale-20 block")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--orbit-reps", type=int, default=2,
+                    help="timed per-vertex orbit calls on each graph (0: skip that leg)")
     ap.add_argument("--cpu-scale", type=int, default=21,
                     help="scale of the CPU oracle's sample of the workload family")
     ap.add_argument("--batch-graphs", type=int, default=4096,
@@ -601,6 +630,11 @@ def main():
              f"{budget['partitions']} partitions, equal {budget['equal_to_resident']}, "
              "phases ms " + ", ".join(f"{k} {v:.0f}" for k, v in budget["ms_phases"].items()))
 
+    orbits = None
+    if args.orbit_reps > 0:
+        orbits = run_orbits_leg(ctx, rp, col, counts, args.orbit_reps)
+        note(f"orbits leg: {orbits['ms']:.1f} ms, totals equal {orbits['totals_equal_counts']}")
+
     digest = source_digest()
     dname = main_leg["dname"]
     traffic = traffic_for(KERNEL_SYMBOL[dname], digest)
@@ -627,6 +661,8 @@ def main():
                                "alg_bytes": leg["alg_bytes"],
                                "ms": float(leg["ms_k"][leg["dom"]])},
                   "kernels": leg["kernels"], "work": leg["work"]}
+        if args.orbit_reps > 0:
+            social["orbits"] = run_orbits_leg(ctx, rps, cols, leg["counts"], args.orbit_reps)
         note(f"social block: {social['value']:.3g} edges/s, parity {social['parity_vs_oracle']}")
 
     batched = run_batch_leg(ctx, args) if args.batch_graphs > 0 else None
@@ -670,6 +706,7 @@ def main():
         "work": main_leg["work"],
         "device_bytes": main_leg["device_bytes"],
         "budget": budget,
+        "orbits": orbits,
         "cpu_baseline": cpu,
         "social": social,
         "batched": batched,
