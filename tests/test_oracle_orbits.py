@@ -161,3 +161,53 @@ def test_relabel_and_union_invariance():
     assert (r[perm] == a).all()
     u = oracle.orbits_esu(*G.disjoint_union(g, h))
     assert (u[:50] == a).all() and (u[50:] == oracle.orbits_esu(*h)).all()
+
+
+# ---------------------------------------------------------------- mutants
+# plausible mistakes in the orbit assignment, each planted in a copy of the
+# oracle source: the closed forms above must catch every one
+ORBIT_MUTANTS = [
+    ("case PATH: return d == 1 ? 4 : 5;", "case PATH: return d == 1 ? 5 : 4;"),
+    ("case STAR: return d == 1 ? 6 : 7;", "case STAR: return d == 1 ? 7 : 6;"),
+    ("case PAW: return d == 1 ? 9 : (d == 2 ? 10 : 11);", "case PAW: return d == 1 ? 10 : (d == 2 ? 9 : 11);"),
+    ("case PAW: return d == 1 ? 9 : (d == 2 ? 10 : 11);", "case PAW: return d == 1 ? 9 : (d == 2 ? 11 : 10);"),
+    ("case DIAMOND: return d == 2 ? 12 : 13;", "case DIAMOND: return d == 2 ? 13 : 12;"),
+    ("for (int j = i + 1; j < 4; j++)\n      if (adjacent(rp, col, s[i], s[j])) { deg[i]++; deg[j]++; }\n  int c = classify",
+     "for (int j = i + 1; j < 4; j++)\n      if (adjacent(rp, col, s[i], s[j])) { deg[i]++; }\n  int c = classify"),
+    ("for (int i = 0; i < 4; i++) orb[(int64_t)s[i] * 11 + orbit_of(c, deg[i]) - 4]++;",
+     "for (int i = 0; i < 3; i++) orb[(int64_t)s[i] * 11 + orbit_of(c, deg[i]) - 4]++;"),
+]
+
+
+@pytest.mark.parametrize("i", range(len(ORBIT_MUTANTS)))
+def test_orbit_mutant_is_caught(tmp_path, i):
+    import ctypes
+    import os
+    import subprocess
+    old, new = ORBIT_MUTANTS[i]
+    src_path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                            "oracle", "m4ref.c")
+    src = open(src_path).read()
+    assert src.count(old) == 1, old
+    path = tmp_path / f"omut{i}.c"
+    path.write_text(src.replace(old, new))
+    lib_path = tmp_path / f"libomut{i}.so"
+    subprocess.run(["gcc", "-O1", "-fopenmp", "-shared", "-fPIC", "-I", os.path.dirname(src_path),
+                    str(path), "-o", str(lib_path)], check=True)
+    lib = ctypes.CDLL(str(lib_path))
+    caught = {}
+    for fn in ("m4ref_orbits_brute", "m4ref_orbits_esu"):
+        f = getattr(lib, fn)
+        f.argtypes = [ctypes.c_int64] + [ctypes.c_void_p] * 3
+        caught[fn] = False
+        for _, make, expected in CLOSED:
+            rp, col = make()
+            rp = np.ascontiguousarray(rp, dtype=np.int64)
+            col = np.ascontiguousarray(col if len(col) else np.zeros(1), dtype=np.int32)
+            n = len(rp) - 1
+            orb = np.zeros((max(n, 1), 11), dtype=np.uint64)
+            rc = f(n, rp.ctypes.data, col.ctypes.data, orb.ctypes.data)
+            if rc != 0 or not (orb[:n] == expected()).all():
+                caught[fn] = True
+                break
+    assert all(caught.values()), caught
