@@ -190,6 +190,22 @@ int m4_count_motifs4(const m4_csr* g, uint64_t out[6]);
 int m4_count_motifs4_ex(m4_ctx* ctx, const m4_csr* g, const m4_opts* opts,
                         uint64_t out[6], m4_stats* st);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the count
+ * of m4_count_motifs4_ex on a CSR already in device memory (g->on_device),
+ * with every workspace carved from a fixed 256 MiB array in device memory
+ * that the library holds on each GPU it runs on until the process ends.  It
+ * calls no hipMalloc / hipFree and no allocating library routine.  The CSR
+ * and out[] stay the caller's.  opts may be NULL; M4_TIMING and
+ * M4_FORCE_PARTITION are ignored and a device budget is M4_EINVAL.  A graph
+ * whose prepared CSR and stage workspace exceed the array is rejected with
+ * M4_ENOMEM before any launch; hub tables or 4-cycle descriptors that do not
+ * fit fail the call with M4_ENOMEM while the stages are planned, before
+ * their kernels run.  Every call on one GPU shares that GPU's array (it
+ * keeps the last call's contents; the call clears what must start at zero):
+ * calls that overlap on one GPU race, so serialise them. */
+int m4_count_motifs4_noalloc(m4_ctx* ctx, const m4_csr* g, const m4_opts* opts, uint64_t out[6]);
+
 /* Per-edge triangle counts t_e = |N(u) & N(v)| for every CSR entry of g, in
  * g's own layout (t_out[p] for col[p]); t_out is a device pointer when
  * g->on_device, else host.  Same anchor kernels as the count. */

@@ -130,6 +130,7 @@ def lib():
                                           ctypes.POINTER(Stats)]
         L.m4_edge_triangles.argtypes = [p, ctypes.POINTER(Csr), ctypes.POINTER(Opts), p]
         L.m4_count_orbits4.argtypes = [p, ctypes.POINTER(Csr), ctypes.POINTER(Opts), p]
+        L.m4_count_motifs4_noalloc.argtypes = [p, ctypes.POINTER(Csr), ctypes.POINTER(Opts), p]
         L.m4_count_batch.argtypes = [p, ctypes.POINTER(Batch), ctypes.POINTER(Opts), p,
                                      ctypes.POINTER(Stats)]
         L.m4_get_tuning.argtypes = [p, ctypes.POINTER(Tuning)]
@@ -245,6 +246,16 @@ class Context:
                                               out, ctypes.byref(st)))
         counts = tuple(int(x) for x in out)
         return (counts, st.to_dict()) if (stats or timing) else counts
+
+    def count_noalloc(self, row_ptr, col, *, flags=0, budget=0, stream=None):
+        """The six counts through the allocation-free entry point (CSR in
+        device memory, workspaces from the library's fixed device array)."""
+        keep = _Keep()
+        g = make_csr(row_ptr, col, keep)
+        o = make_opts(flags, budget, 0, self._stream_for(row_ptr, stream))
+        out = (ctypes.c_uint64 * 6)()
+        self._check(lib().m4_count_motifs4_noalloc(self.h, ctypes.byref(g), ctypes.byref(o), out))
+        return tuple(int(x) for x in out)
 
     def edge_triangles(self, row_ptr, col, *, flags=0, stream=None, tri_wave_max=0):
         """t_e for every CSR entry, in the input layout (numpy uint32 for host

@@ -18,6 +18,18 @@ using namespace m4;
 namespace m4 {
 
 void DevBuf::ensure(size_t bytes, hipStream_t s, bool exact) {
+  if (pool) {
+    if (bytes <= cap) return;
+    const size_t off = ptr ? (size_t)(ptr - pool->base) : ((pool->used + 255) & ~size_t(255));
+    if ((ptr && off + cap != pool->used) || off + bytes > pool->cap)
+      throw Fail(M4_ENOMEM, "workspace of " + std::to_string(bytes) +
+                                " bytes does not fit in the fixed scratch of " +
+                                std::to_string(pool->cap) + " bytes");
+    ptr = pool->base + off;
+    cap = bytes;
+    pool->used = off + bytes;
+    return;
+  }
   if (exact ? bytes == cap : bytes <= cap) return;
   if (ptr) {
     M4_HIP(hipStreamSynchronize(s));
@@ -41,7 +53,7 @@ void DevBuf::ensure(size_t bytes, hipStream_t s, bool exact) {
 }
 
 void DevBuf::release() {
-  if (ptr) (void)hipFree(ptr);
+  if (ptr && !pool) (void)hipFree(ptr);
   ptr = nullptr;
   cap = 0;
 }
@@ -155,6 +167,7 @@ extern "C" int m4_ctx_create(int device, m4_ctx** out) {
     for (int i = 0; i < kNumEvents; i++) M4_HIP(hipEventCreate(&c->ev[i]));
     for (int k = 0; k < M4_NK; k++)
       for (int j = 0; j < 2; j++) M4_HIP(hipEventCreate(&c->ktimer.ev[k][j]));
+    noalloc_setup(device);
   } catch (const HipFail& f) {
     (void)hipGetLastError();
     m4_ctx_destroy(c);
@@ -255,8 +268,8 @@ Tuning tuning_for(const m4_ctx* c, const m4_opts* o) {
   tu.c4_light_max = std::max(0, std::min(tu.c4_light_max, C4_HASH_SLOTS / 2));
   tu.c4_med_max = std::max(0, std::min(tu.c4_med_max, 3 * C4_MED_SLOTS / 4));
   // the binned 4-cycle owners take scratch sized by the CU count, which a
-  // device budget does not provide for
-  if (o && o->device_budget_bytes > 0) tu.c4_bin_win = 0;
+  // device budget and the fixed scratch do not provide for
+  if ((o && o->device_budget_bytes > 0) || c->no_alloc) tu.c4_bin_win = 0;
   return tu;
 }
 

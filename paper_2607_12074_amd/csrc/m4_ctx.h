@@ -6,13 +6,24 @@
 
 namespace m4 {
 
+// A fixed region of device memory handed out front to back (the
+// allocation-free entry point's workspaces).
+struct ScratchPool {
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+};
+
 // Growable device buffer owned by a context.
 // ensure() over-allocates by 1/8 (plus 1 MiB) so that slowly growing inputs
 // do not reallocate every call; exact = true allocates exactly `bytes` and
-// also shrinks a larger buffer (the budgeted path must not hold more).
+// also shrinks a larger buffer (the budgeted path must not hold more).  With
+// a pool, ensure() carves the bytes from it instead (a buffer can grow only
+// while it is the pool's last carve) and fails with M4_ENOMEM when they do
+// not fit; nothing is allocated or freed.
 struct DevBuf {
   char* ptr = nullptr;
   size_t cap = 0;
+  ScratchPool* pool = nullptr;
   void ensure(size_t bytes, hipStream_t s, bool exact = false);
   void release();
 };
@@ -33,6 +44,11 @@ int check_csr_args(const m4_csr* g);
 Tuning tuning_for(const m4_ctx* c, const m4_opts* o);
 void run_resident(m4_ctx* c, const int64_t* rp, const int32_t* col, int64_t n, int64_t nnz,
                   const m4_opts* o, hipStream_t s, Prep& P, bool want_timing);
+// m4_noalloc.hip: the fixed scratch of the allocation-free entry point;
+// noalloc_setup() looks up its address on the current device (once per
+// device, from m4_ctx_create; a failed lookup leaves that entry point
+// reporting M4_EDEVICE on the device)
+void noalloc_setup(int device);
 
 // m4_part.hip
 bool needs_partition(m4_ctx* c, const m4_csr* g, const m4_opts* o);
@@ -72,6 +88,7 @@ struct m4_ctx {
   m4::PartState* part = nullptr;
   m4::BasisChoice basis;                  // cycle/path basis of the last resident count
   unsigned long long cost_pair[2] = {0, 0};  // its objective's inputs, read back
+  bool no_alloc = false;  // inside the allocation-free entry point
   // device bytes the context holds now (workspaces, batch buffers, Scal)
   size_t held_bytes() const;
   // frees every workspace except the budgeted path's (c->extra)
