@@ -301,7 +301,7 @@ inline unsigned blocks_for(int64_t n, int nt) { return (unsigned)ceil_div(n > 0 
 
 // Degree thresholds of the row-sort classes; the same table decides which
 // kernel sorts each rank range.
-static const int kThr[] = {1, 8, 16, 32, 64, 256, 1024, 2048, 2048};
+static const int kThr[] = {1, 8, 16, 32, 64, 256, 1024, 2048, 8192, 16384};
 static constexpr int kNThr = sizeof(kThr) / sizeof(kThr[0]);
 
 void sort_rows(const int64_t* rp, const int32_t* col, const int32_t* perm, const int32_t* rank,
@@ -332,8 +332,16 @@ void sort_rows(const int64_t* rp, const int32_t* col, const int32_t* perm, const
   if (b[7] > b[6])
     k_row_bitonic<2048, 512><<<(unsigned)(b[7] - b[6]), 512, 0, s>>>(
         rp, col, perm, rank, nptr, dr, b[6], ncol, dlo, dplus, r_base);
-  if (r_hi > b[8])
-    k_row_bitmap<<<(unsigned)(r_hi - b[8]), BM_NT, 0, s>>>(rp, col, perm, rank, nptr, dr, n, b[8],
+  // up to 16384 entries a row is one bitonic sort in LDS (gathering each
+  // entry's rank once); longer rows take the bitmap windows
+  if (b[8] > b[7])
+    k_row_bitonic<8192, 1024><<<(unsigned)(b[8] - b[7]), 1024, 0, s>>>(
+        rp, col, perm, rank, nptr, dr, b[7], ncol, dlo, dplus, r_base);
+  if (b[9] > b[8])
+    k_row_bitonic<16384, 1024><<<(unsigned)(b[9] - b[8]), 1024, 0, s>>>(
+        rp, col, perm, rank, nptr, dr, b[8], ncol, dlo, dplus, r_base);
+  if (r_hi > b[9])
+    k_row_bitmap<<<(unsigned)(r_hi - b[9]), BM_NT, 0, s>>>(rp, col, perm, rank, nptr, dr, n, b[9],
                                                            ncol, dlo, dplus, r_base);
 }
 

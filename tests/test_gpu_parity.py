@@ -59,6 +59,20 @@ def test_hub_rows_and_window_counters(ctx):
                              comb(3, 2) * comb(70000, 2), 0, 0)
 
 
+def test_every_row_sort_class(ctx):
+    # rows of 3000, 6000, 12000 and 20000 entries (bitonic sorts of 4096,
+    # 8192 and 16384 slots, then the bitmap windows) beside short ones: the
+    # per-edge triangle counts come back in the input layout, so every
+    # sorted row is checked entry by entry, and the counts are the oracle's
+    parts = [G.wheel(3000), G.wheel(6000), G.star(12000), G.wheel(20000), gg.gnm(2000, 9000, 5)]
+    g = parts[0]
+    for h in parts[1:]:
+        g = G.disjoint_union(g, h)
+    ref, t_ref = oracle.closure(*g, want_t=True)
+    assert ctx.count(*g) == ref
+    assert (ctx.edge_triangles(*g) == t_ref).all()
+
+
 def test_multi_window_long_segments(ctx):
     # A 300000-cycle below K_{50,200}: the cycle's degree-2 ranks fill more
     # than one window of 4-bit counters (262144 per window), so the 4-cycle
