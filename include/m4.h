@@ -87,7 +87,8 @@ typedef struct {
   uint32_t cache_rows;          /* signature-cache rows per owner (0 = unlimited)  */
   void* hip_stream;             /* hipStream_t to run on (NULL = context stream)   */
   /* tuning (0 = library default / autotuned value) */
-  int32_t tri_wave_max;   /* owners with out-degree <= this use one wavefront      */
+  int32_t tri_wave_max;   /* owners with out-degree <= this use one wavefront
+                             (overrides both of the context's wave bounds)     */
   int32_t c4_light_max;   /* owners with wedge bound <= this use the LDS hash      */
   int32_t c4_med_max;     /* ... <= this the medium LDS hash (-1: none)            */
   int32_t reserved[3];
@@ -240,7 +241,9 @@ int m4_count_orbits4(m4_ctx* ctx, const m4_csr* g, const m4_opts* opts, uint64_t
  * context's tuning is unchanged. */
 typedef struct {
   int32_t tri_wave_max;  /* single graph: owners with out-degree <= this use one
-                            64-thread workgroup (2..64, default 32)            */
+                            64-thread workgroup (2..64, default 32), while the
+                            out-lists (4 m bytes) fit in the 256 MiB Infinity
+                            Cache                                              */
   int32_t c4_light_max;  /* single graph: owners with wedge bound <= this use the
                             LDS hash (1..2048, default 2048)                   */
   int32_t batch_variant; /* fused batched kernel: 0 = 1024 threads with 96 KiB of
@@ -257,7 +260,7 @@ typedef struct {
                             (c4_light_max, c4_med_max] use the 16384-slot LDS
                             hash in one pass, heavier ones the counter windows
                             (0 = no medium bucket, else up to 12288, default
-                            6144)                                             */
+                            12288)                                            */
   int32_t probe_w;       /* single graph: a triangle row is probed in the hub
                             table when probe_w * (probes) < 3 * (elements a
                             scan would read) (1..256, default 4), while the
@@ -287,6 +290,8 @@ typedef struct {
   int32_t probe_w_far;   /* single graph: probe_w when the hub tables exceed
                             the Infinity Cache, so that a probe is a line
                             read from HBM (1..256, default 16)                */
+  int32_t tri_wave_far;  /* single graph: tri_wave_max when the out-lists
+                            exceed the Infinity Cache (2..64, default 64)     */
 } m4_tuning;
 
 int m4_get_tuning(const m4_ctx* ctx, m4_tuning* out);

@@ -86,7 +86,8 @@ class Tuning(ctypes.Structure):
                 ("hub_min", ctypes.c_int32), ("c4_med_max", ctypes.c_int32),
                 ("probe_w", ctypes.c_int32), ("c4_med_win", ctypes.c_int32),
                 ("c4_bin_win", ctypes.c_int32), ("c4_bin_cap", ctypes.c_int32),
-                ("c4_bin_dense", ctypes.c_int32), ("probe_w_far", ctypes.c_int32)]
+                ("c4_bin_dense", ctypes.c_int32), ("probe_w_far", ctypes.c_int32),
+                ("tri_wave_far", ctypes.c_int32)]
 
     def to_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}

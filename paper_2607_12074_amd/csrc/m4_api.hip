@@ -260,7 +260,7 @@ void stage_input(m4_ctx* c, const m4_csr* g, hipStream_t s, const int64_t** rp,
 
 Tuning tuning_for(const m4_ctx* c, const m4_opts* o) {
   Tuning tu = c->tune;
-  if (o && o->tri_wave_max > 0) tu.tri_wave_max = o->tri_wave_max;
+  if (o && o->tri_wave_max > 0) tu.tri_wave_max = tu.tri_wave_far = o->tri_wave_max;
   if (o && o->c4_light_max > 0) tu.c4_light_max = o->c4_light_max;
   if (o && o->c4_med_max != 0) tu.c4_med_max = o->c4_med_max < 0 ? 0 : o->c4_med_max;
   // the light table holds C4_HASH_SLOTS keys at load <= 1/2, the medium one

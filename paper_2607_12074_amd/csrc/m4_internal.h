@@ -117,7 +117,7 @@ struct Arena {
 struct Tuning {
   int tri_wave_max = 32;    // <= WAVE
   int c4_light_max = 2048;  // wedge bound for the hash bucket
-  int c4_med_max = 6144;    // wedge bound for the one-pass medium hash (0: no medium bucket)
+  int c4_med_max = 12288;   // wedge bound for the one-pass medium hash (0: no medium bucket)
   int grid_mult = 8;        // persistent blocks per CU for light kernels
   int batch_variant = 0;    // batched kernel: 0 = 1024 threads / 96 KiB, 1 = 512 / 40 KiB
   int batch_light = 128;    // batched kernel: wedge bound of the wavefront hash
@@ -129,6 +129,7 @@ struct Tuning {
   int c4_bin_cap = 0;       // endpoints of a binning workgroup's scratch (0: 2^20)
   int c4_bin_dense = 8192;  // endpoints per window from which an owner keeps dense windows (0: never)
   int probe_w_far = 16;     // probe_w when the hub tables do not fit in the Infinity Cache
+  int tri_wave_far = 64;    // tri_wave_max when the out-lists do not fit in the Infinity Cache
   // weights of the anchor-selection objective, from stage times measured on
   // the MI355X over graphs of 10^2 to 10^7 edges: ns per wedge endpoint
   // bound, fixed us of the wedge stage (its plan kernels and host

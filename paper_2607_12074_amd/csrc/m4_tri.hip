@@ -217,7 +217,10 @@ Launch tri_plan(const Prep& P, Scal* scal, const Tuning& tu, uint32_t flags, uin
   int64_t* start = tmp.take<int64_t>(17);
   if (!key || !order || !rtmp || !start) throw Fail(M4_EINTERNAL, "workspace too small (tri)");
   fill_u32(&scal->work[0], 0, 8, s);
-  int wave_max = tu.tri_wave_max < 2 ? 2 : (tu.tri_wave_max > 64 ? 64 : tu.tri_wave_max);
+  // one wavefront per owner reaches more owners when the out-lists it scans
+  // stream from HBM rather than from the Infinity Cache
+  const int wave_req = (size_t)P.m * 4 > kInfinityCacheBytes ? tu.tri_wave_far : tu.tri_wave_max;
+  int wave_max = wave_req < 2 ? 2 : (wave_req > 64 ? 64 : wave_req);
   k_tri_keys<<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(P.dplus, n, P.own_lo, P.hi(), wave_max,
                                                          key, scal);
   radix_pass(key, nullptr, n, 0, 4, nullptr, order, rtmp, start, s);

@@ -41,6 +41,7 @@ void to_public(const Tuning& t, m4_tuning* out) {
   out->c4_bin_cap = t.c4_bin_cap;
   out->c4_bin_dense = t.c4_bin_dense;
   out->probe_w_far = t.probe_w_far;
+  out->tri_wave_far = t.tri_wave_far;
 }
 
 }  // namespace
@@ -61,7 +62,7 @@ extern "C" int m4_set_tuning(m4_ctx* ctx, const m4_tuning* t) {
       t->c4_med_win < 0 || t->c4_med_win > 65536 || t->c4_bin_win < 0 || t->c4_bin_win > 65536 ||
       (t->c4_bin_cap != 0 && (t->c4_bin_cap < 64 || t->c4_bin_cap > (1 << 24))) ||
       (t->c4_bin_dense != 0 && (t->c4_bin_dense < 64 || t->c4_bin_dense > (1 << 20))) ||
-      t->probe_w_far < 1 || t->probe_w_far > 256)
+      t->probe_w_far < 1 || t->probe_w_far > 256 || t->tri_wave_far < 2 || t->tri_wave_far > 64)
     return set_error(ctx, M4_EINVAL, "tuning value out of range");
   ctx->tune.tri_wave_max = t->tri_wave_max;
   ctx->tune.c4_light_max = t->c4_light_max;
@@ -75,6 +76,7 @@ extern "C" int m4_set_tuning(m4_ctx* ctx, const m4_tuning* t) {
   ctx->tune.c4_bin_cap = t->c4_bin_cap;
   ctx->tune.c4_bin_dense = t->c4_bin_dense;
   ctx->tune.probe_w_far = t->probe_w_far;
+  ctx->tune.tri_wave_far = t->tri_wave_far;
   return M4_OK;
 }
 
@@ -128,7 +130,8 @@ extern "C" int m4_autotune(m4_ctx* ctx, const m4_csr* graph, const m4_batch* bat
       for (int w : waves)
         for (int l : lights) {
           Tuning t = start;
-          t.tri_wave_max = w;
+          t.tri_wave_max = w;  // the sample graph decides which of the two bounds applies
+          t.tri_wave_far = w;
           t.c4_light_max = l;
           const int rc = try_cfg(t);
           if (rc != M4_OK) {

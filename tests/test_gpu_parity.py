@@ -235,7 +235,8 @@ def test_caller_stream_and_tuning_bounds(ctx):
     # out-of-range thresholds are rejected and leave the tuning unchanged
     before = ctx.get_tuning()
     for bad in ({"c4_med_max": 20000}, {"c4_med_win": -1}, {"probe_w": 0},
-                {"tri_wave_max": 65}, {"hub_min": 2}):
+                {"tri_wave_max": 65}, {"hub_min": 2}, {"tri_wave_far": 1}, {"probe_w_far": 300},
+                {"c4_bin_dense": 32}):
         with pytest.raises(m4.M4Error) as e:
             ctx.set_tuning(**bad)
         assert e.value.code == m4.M4_EINVAL
