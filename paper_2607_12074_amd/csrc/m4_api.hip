@@ -120,8 +120,9 @@ size_t stage_tmp_bytes(int64_t n, int64_t nnz, int64_t dmax, int num_cu) {
   return std::max(build, tri + c4_tmp_bytes(n)) + (1 << 16);
 }
 
-size_t c4_tmp_bytes(int64_t n) {
-  return 2 * align256((size_t)(n + 1) * 8 + 8) + 4 * align256((size_t)n * 4 + 4) +
+size_t c4_tmp_bytes(int64_t n, bool full_rows) {
+  return 2 * align256((size_t)(n + 1) * 8 + 8) + 3 * align256((size_t)n * 4 + 4) +
+         (full_rows ? align256((size_t)n * 16 + 16) : 0) +
          align256(radix_tmp_elems(n, C4_KEY_BITS) * 8) + align256(scan_tmp_elems(n) * 8) +
          align256(32 * 8) + 4096;
 }

@@ -431,7 +431,7 @@ __global__ __launch_bounds__(256) void k_c4_desc(const int32_t* __restrict__ ord
                                                  const int64_t* __restrict__ nptr,
                                                  const int32_t* __restrict__ dlo,
                                                  const int32_t* __restrict__ ncol,
-                                                 const int32_t* __restrict__ lowcut,
+                                                 const int4* __restrict__ vmeta,
                                                  const int32_t* __restrict__ row_len, int64_t r1,
                                                  int4* __restrict__ desc,
                                                  int64_t* __restrict__ seg_pre,
@@ -446,12 +446,20 @@ __global__ __launch_bounds__(256) void k_c4_desc(const int32_t* __restrict__ ord
     int64_t len = 0, c = 0, e = 0;
     if (i < nl) {
       const int32_t v = ncol[base + i];
-      const int64_t rs = nptr[v];
-      const int64_t rend = row_len ? rs + row_len[v] : nptr[v + 1];
-      // u is an out-neighbour of v: search the out-part of row v
-      e = lower_index(ncol, rs + dlo[v], rend, u);
-      // first entry >= r1: precomputed for full rows, searched for stored prefixes
-      c = lowcut ? rs + lowcut[v] : lower_index(ncol, rs, e, (int32_t)r1);
+      if (vmeta) {
+        // full rows: one 16-byte record per vertex
+        const int4 m = vmeta[v];
+        const int64_t rs = m.x;
+        // u is an out-neighbour of v: search the out-part of row v
+        e = lower_index(ncol, rs + m.z, rs + m.y, u);
+        c = rs + m.w;
+      } else {
+        const int64_t rs = nptr[v];
+        const int64_t rend = row_len ? rs + row_len[v] : nptr[v + 1];
+        e = lower_index(ncol, rs + dlo[v], rend, u);
+        // first entry >= r1, searched in the stored prefix
+        c = lower_index(ncol, rs, e, (int32_t)r1);
+      }
       if (c > e) c = e;
       len = e - c;
     }
@@ -469,14 +477,16 @@ __global__ __launch_bounds__(256) void k_c4_desc(const int32_t* __restrict__ ord
   if (threadIdx.x == 0) seg_cnt[h] = (int32_t)kept;
 }
 
-// entries below r1 (degree <= 1) at the head of every sorted row
-__global__ void k_lowcut(const int64_t* __restrict__ nptr, const int32_t* __restrict__ ncol,
-                         const int32_t* __restrict__ row_len, int64_t n, int64_t r1,
-                         int32_t* __restrict__ lowcut) {
+// per full row: {row offset, degree, lower neighbours, entries below r1
+// (degree <= 1) at its head}; row offsets fit 32 bits (CSR positions do)
+__global__ void k_vmeta(const int64_t* __restrict__ nptr, const int32_t* __restrict__ ncol,
+                        const int32_t* __restrict__ dr, const int32_t* __restrict__ dlo, int64_t n,
+                        int64_t r1, int4* __restrict__ vmeta) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
-  const int64_t rend = row_len ? nptr[v] + row_len[v] : nptr[v + 1];
-  lowcut[v] = (int32_t)(lower_index(ncol, nptr[v], rend, (int32_t)r1) - nptr[v]);
+  const int64_t rs = nptr[v];
+  const int32_t cut = (int32_t)(lower_index(ncol, rs, nptr[v + 1], (int32_t)r1) - rs);
+  vmeta[v] = make_int4((int)rs, dr[v], dlo[v], cut);
 }
 
 __global__ void k_c4_heavy_len(const int32_t* __restrict__ order, const int64_t* __restrict__ start,
@@ -1486,8 +1496,10 @@ Launch c4_plan(const Prep& P, const Classes& C, Scal* scal, const Tuning& tu, ui
   int32_t* hlen = tmp.take<int32_t>(n);
   int64_t* seg_off = tmp.take<int64_t>(n + 1);
   int64_t* stmp = tmp.take<int64_t>(scan_tmp_elems(n));
-  int32_t* lowcut = tmp.take<int32_t>(n);
-  if (!wub || !key || !order || !rtmp || !start || !hlen || !seg_off || !stmp || !lowcut)
+  // per-row records of full rows (a partition stores row prefixes instead)
+  int4* vmeta = P.row_len ? nullptr : tmp.take<int4>(n);
+  if (!wub || !key || !order || !rtmp || !start || !hlen || !seg_off || !stmp ||
+      (!P.row_len && !vmeta))
     throw Fail(M4_EINTERNAL, "workspace too small (c4)");
   fill_u32(&scal->work_c4[0], 0, 8, s);
   // zone bounds first: the planner needs every owner's window count
@@ -1588,9 +1600,9 @@ Launch c4_plan(const Prep& P, const Classes& C, Scal* scal, const Tuning& tu, ui
       if (kt) kt->begin(M4_K_C4_DESC, ls);
       // with stored prefixes only the partition's rows are valid: no full pass
       if (!P.row_len)
-        k_lowcut<<<blocks_for(n, 256), 256, 0, ls>>>(P.nptr, P.ncol, P.row_len, n, C.r1, lowcut);
+        k_vmeta<<<blocks_for(n, 256), 256, 0, ls>>>(P.nptr, P.ncol, P.dr, P.dlo, n, C.r1, vmeta);
       k_c4_desc<<<(unsigned)H, 256, 0, ls>>>(order, start, seg_off, P.nptr, P.dlo, P.ncol,
-                                             P.row_len ? nullptr : lowcut, P.row_len, C.r1,
+                                             P.row_len ? nullptr : vmeta, P.row_len, C.r1,
                                              desc, seg_pre, seg_cnt);
       if (kt) kt->end(M4_K_C4_DESC, ls);
     }

@@ -36,7 +36,8 @@ struct PartState;
 size_t prep_bytes(int64_t n, int64_t nnz);
 Prep carve_prep(char* base, int64_t n, int64_t nnz);
 size_t stage_tmp_bytes(int64_t n, int64_t nnz, int64_t dmax, int num_cu);
-size_t c4_tmp_bytes(int64_t n);
+// full_rows: the per-row records of resident runs (partitions store prefixes)
+size_t c4_tmp_bytes(int64_t n, bool full_rows = true);
 int set_error(m4_ctx* ctx, int code, const std::string& msg);
 // status and message of the error bits a call left in Scal::err
 int scal_error(m4_ctx* ctx, int err);

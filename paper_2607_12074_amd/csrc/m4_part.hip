@@ -501,7 +501,7 @@ int count_partitioned(m4_ctx* c, const m4_csr* g, const m4_opts* o, uint64_t out
   fill_u32(P.t, 0, (size_t)m, s);
   const size_t fixed_used = D.used;
   const size_t tri_tmp = 2 * al(n * 4 + 4) + al(radix_tmp_elems(n, 4) * 8) + 4096;
-  const size_t c4_tmp = c4_tmp_bytes(n);
+  const size_t c4_tmp = c4_tmp_bytes(n, false);
   // scratch that a kernel stage sizes at run time comes from the tail of the
   // budget region, after the stage's work arrays
   size_t scratch_floor = 0;
