@@ -1231,7 +1231,7 @@ __global__ __launch_bounds__(BN_NT, 4) void k_c4_bin(C4Args A) {
       // than BF_GROUP endpoints alone (a dense target; it always ends its
       // stretch).  Each bucket's target goes to off; the scatter state sits in
       // the counter regions, unused until pass 3: per target its write
-      // cursor (bit 31: dense), and for the first BF_NTS targets a BF_SB-entry
+      // cursor (bit 31: dense), and for the last BF_NTS targets a BF_SB-entry
       // staging buffer (its fill and completion counts, and a tail cursor for
       // endpoints that arrive while it is full).  Targets start at multiples
       // of 8 scratch entries, so a full buffer leaves as aligned 16-byte
@@ -1274,6 +1274,7 @@ __global__ __launch_bounds__(BN_NT, 4) void k_c4_bin(C4Args A) {
         __syncthreads();
         // padded starts: each target's count rounded up to a multiple of 8
         const int nt = (int)ntot;
+        const int sb = nt > BF_NTS ? nt - BF_NTS : 0;  // first target with a buffer
         const uint32_t span = (uint32_t)(off_end - p0);
         uint32_t st[PER + 1], kinds = 0, psum = 0;
         for (int k = 0; k <= PER; k++) {
@@ -1290,9 +1291,9 @@ __global__ __launch_bounds__(BN_NT, 4) void k_c4_bin(C4Args A) {
           if (tt < nt) {
             const uint32_t c = st[k + 1] - st[k];
             head[tt] = ps | (((kinds >> k) & 1u) << 31);
-            if (tt < BF_NTS) {
-              tail[tt] = tend[tt] = ps + c;
-              fill[tt] = done[tt] = 0;
+            if (tt >= sb) {
+              tail[tt - sb] = tend[tt - sb] = ps + c;
+              fill[tt - sb] = done[tt - sb] = 0;
             }
             ps += (c + 7) & ~7u;
           }
@@ -1300,22 +1301,27 @@ __global__ __launch_bounds__(BN_NT, 4) void k_c4_bin(C4Args A) {
       }
       __syncthreads();
       const int ntargets = uni(s_nt);
+      // the last BF_NTS targets (the highest ranks, whose buckets of 32-bit
+      // counters span the fewest ranks and hold the most endpoints) have
+      // staging buffers
+      const int sbase = ntargets > BF_NTS ? ntargets - BF_NTS : 0;
       // ---- pass 2: scatter the range's endpoints by target (one step in
       // flight: its stores, not its loads, bound this pass)
       bin_walk<1>(A.ncol, D, pre, nl, q_lo, q_hi, s_lo, [&](int32_t x, bool valid) {
         bool flush = false;
-        int t = 0;
+        int t = 0, sl = 0;
         if (valid) {
           const int w = fbin_of(A, x);
           if (w >= b0 && w < b1) {
             t = off[w];
-            if (t < BF_NTS) {
-              const uint32_t slot = atomicAdd(&fill[t], 1u);
+            sl = t - sbase;
+            if (sl >= 0) {
+              const uint32_t slot = atomicAdd(&fill[sl], 1u);
               if (slot < BF_SB) {
-                stage[t * BF_SB + slot] = x;
-                flush = atomicAdd(&done[t], 1u) == BF_SB - 1;
+                stage[sl * BF_SB + slot] = x;
+                flush = atomicAdd(&done[sl], 1u) == BF_SB - 1;
               } else {
-                bins[atomicSub(&tail[t], 1u) - 1] = x;
+                bins[atomicSub(&tail[sl], 1u) - 1] = x;
               }
             } else {
               bins[atomicAdd(&head[t], 1u) & 0x7fffffffu] = x;
@@ -1326,7 +1332,7 @@ __global__ __launch_bounds__(BN_NT, 4) void k_c4_bin(C4Args A) {
           // every slot of the buffer is written: it leaves as aligned
           // 16-byte stores, two at a time, and only then are the counters
           // reset (no new entry lands in the buffer before that)
-          const int4* sv = reinterpret_cast<const int4*>(stage + t * BF_SB);
+          const int4* sv = reinterpret_cast<const int4*>(stage + sl * BF_SB);
           const uint32_t at = atomicAdd(&head[t], (uint32_t)BF_SB) & 0x7fffffffu;
           int4* dst = reinterpret_cast<int4*>(bins + at);
 #pragma unroll
@@ -1335,21 +1341,21 @@ __global__ __launch_bounds__(BN_NT, 4) void k_c4_bin(C4Args A) {
             dst[k] = v0;
             dst[k + 1] = v1;
           }
-          done[t] = 0;
-          fill[t] = 0;
+          done[sl] = 0;
+          fill[sl] = 0;
         }
       });
       reads += (unsigned long long)total;
       __syncthreads();
       // buffers still holding entries, then the target ends (bit 31: dense)
       // move to off[b0 ..) and the regions are cleared
-      for (int t = tid; t < ntargets && t < BF_NTS; t += BN_NT) {
+      for (int t = sbase + tid; t < ntargets; t += BN_NT) {
         const uint32_t at = head[t] & 0x7fffffffu;
-        for (uint32_t k = 0; k < done[t]; k++) bins[at + k] = stage[t * BF_SB + k];
+        for (uint32_t k = 0; k < done[t - sbase]; k++) bins[at + k] = stage[(t - sbase) * BF_SB + k];
       }
       __syncthreads();
       for (int t = tid; t < ntargets; t += BN_NT)
-        off[b0 + t] = (int32_t)((t < BF_NTS ? tend[t] : head[t] & 0x7fffffffu) |
+        off[b0 + t] = (int32_t)((t >= sbase ? tend[t - sbase] : head[t] & 0x7fffffffu) |
                                 (head[t] & 0x80000000u));
       __syncthreads();
       for (int i = tid; i < BN_NW * BF_WORDS / 4; i += BN_NT) cnt4[i] = make_uint4(0, 0, 0, 0);
