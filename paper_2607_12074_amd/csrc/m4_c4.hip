@@ -886,6 +886,7 @@ constexpr int BF_BIG = 4096;     // dense buckets above this: the whole block
 constexpr int BF_BIGLIST = 48;
 constexpr int BF_SB = 16;        // staging buffer entries per target (four 16-byte stores)
 constexpr int BF_NTS = 620;      // targets with a staging buffer (20 words each)
+constexpr int BF_PAD = 16;       // targets start at multiples of this many entries
 static_assert((int64_t)C4_BIN_KMAX * C4_WIN_WORDS <= (int64_t)BF_KMAX * BF_WORDS,
               "a binned owner's fine buckets must fit the LDS histogram");
 static_assert(2 * BF_GROUP <= BF_HSLOTS / 2, "a hash group must keep its table half empty");
@@ -1120,7 +1121,7 @@ __global__ __launch_bounds__(BN_NT, 4) void k_c4_bin(C4Args A) {
   const int64_t b0i = A.start[A.bucket], cnt_items = A.start[A.bucket + 1] - b0i;
   const int64_t hbase = b0i - A.start[CB_WIN];
   // per block: the scratch plus up to 7 padding entries per target
-  int32_t* bins = A.bins + (int64_t)blockIdx.x * (A.bin_cap + 8 * BF_KMAX);
+  int32_t* bins = A.bins + (int64_t)blockIdx.x * (A.bin_cap + BF_PAD * BF_KMAX);
   uint32_t* mycnt = cnt + wid * BF_WORDS;
   u128_t acc = 0;
   // counters kept equal across a wave (scalar registers); lane 0 of each
@@ -1272,7 +1273,7 @@ __global__ __launch_bounds__(BN_NT, 4) void k_c4_bin(C4Args A) {
         }
         if (tid == 0) s_nt = (int)ntot;
         __syncthreads();
-        // padded starts: each target's count rounded up to a multiple of 8
+        // padded starts: each target's count rounded up to a multiple of BF_PAD
         const int nt = (int)ntot;
         const int sb = nt > BF_NTS ? nt - BF_NTS : 0;  // first target with a buffer
         const uint32_t span = (uint32_t)(off_end - p0);
@@ -1284,7 +1285,7 @@ __global__ __launch_bounds__(BN_NT, 4) void k_c4_bin(C4Args A) {
           st[k] &= 0x7fffffffu;
         }
         for (int k = 0; k < PER; k++)
-          if (tid * PER + k < nt) psum += (st[k + 1] - st[k] + 7) & ~7u;
+          if (tid * PER + k < nt) psum += (st[k + 1] - st[k] + BF_PAD - 1) & ~(BF_PAD - 1u);
         uint32_t ps = (uint32_t)block_excl_scan64<BN_NT>(psum, nullptr);
         for (int k = 0; k < PER; k++) {
           const int tt = tid * PER + k;
@@ -1295,7 +1296,7 @@ __global__ __launch_bounds__(BN_NT, 4) void k_c4_bin(C4Args A) {
               tail[tt - sb] = tend[tt - sb] = ps + c;
               fill[tt - sb] = done[tt - sb] = 0;
             }
-            ps += (c + 7) & ~7u;
+            ps += (c + BF_PAD - 1) & ~(BF_PAD - 1u);
           }
         }
       }
@@ -1370,7 +1371,9 @@ __global__ __launch_bounds__(BN_NT, 4) void k_c4_bin(C4Args A) {
       constexpr int HPER = (2 * BF_GROUP + WAVE - 1) / WAVE;  // hash-target endpoints per lane
       // target t occupies [tbeg(t), its end): ends are exact, starts padded
       auto tbeg = [&](int t) -> int64_t {
-        return t == 0 ? 0 : (int64_t)(((uint32_t)off[b0 + t - 1] & 0x7fffffffu) + 7 & ~7u);
+        return t == 0 ? 0
+                      : (int64_t)((((uint32_t)off[b0 + t - 1] & 0x7fffffffu) + BF_PAD - 1) &
+                                  ~(BF_PAD - 1u));
       };
       auto grab = [&]() {
         int g = 0;
@@ -1562,9 +1565,10 @@ Launch c4_plan(const Prep& P, const Classes& C, Scal* scal, const Tuning& tu, ui
     size_t bb = 0;
     if (HB > 0) {
       const int64_t cap = tu.c4_bin_cap > 0 ? tu.c4_bin_cap : int64_t(1) << 20;
-      bin_cap = (std::min<int64_t>(cap, std::max<int64_t>(P.nnz, 1)) + 7) & ~int64_t(7);
+      bin_cap = (std::min<int64_t>(cap, std::max<int64_t>(P.nnz, 1)) + BF_PAD - 1) &
+                ~int64_t(BF_PAD - 1);
       bin_grid = (unsigned)std::min<int64_t>(2 * (int64_t)num_cu, HB);
-      bb = (size_t)bin_grid * (size_t)(bin_cap + 8 * BF_KMAX) * 4;
+      bb = (size_t)bin_grid * (size_t)(bin_cap + BF_PAD * BF_KMAX) * 4;
     }
     char* scr = big_scratch(db + cb + pb + bb);
     if (!scr) throw Fail(M4_ENOMEM, "no room for 4-cycle segment descriptors");
