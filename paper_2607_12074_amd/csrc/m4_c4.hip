@@ -419,9 +419,10 @@ __global__ __launch_bounds__(NT) void k_c4_hash(C4Args A) {
 
 // -------------------------------------------------------- window bucket
 // Segment descriptors of the window and binned owners: for lower neighbour v
-// of owner u the cursor into row v (first entry >= r1), the position of u in
-// row v (the segment's end: entries from there on are not below u), and the
-// values at the cursor and 7 entries after it.  Only non-empty segments are
+// of owner u the cursor into row v (first entry >= r1), the segment's end
+// (for a binned owner the position of u in row v: entries from there on are
+// not below u; for a window owner the row's end), and the values at the
+// cursor and 7 entries after it.  Only non-empty segments are
 // kept (a lower neighbour of degree 1, say, has none), packed from the
 // owner's first slot; seg_cnt[h] is their number and seg_pre (binned owners
 // only) the exclusive prefix of their lengths.  One block per owner.
@@ -440,6 +441,10 @@ __global__ __launch_bounds__(256) void k_c4_desc(const int32_t* __restrict__ ord
   const int32_t u = order[start[CB_WIN] + h];
   const int64_t so = seg_off[h], base = nptr[u];
   const int nl = dlo[u];
+  // binned owners walk positions and need each segment's exact end (u's
+  // place in the row); the window kernel stops at u by value, so its
+  // segments may run to the row's end
+  const bool exact = h >= start[CB_BIN] - start[CB_WIN];
   int64_t run = 0, kept = 0;
   for (int i0 = 0; i0 < nl; i0 += 256) {
     const int i = i0 + (int)threadIdx.x;
@@ -451,12 +456,12 @@ __global__ __launch_bounds__(256) void k_c4_desc(const int32_t* __restrict__ ord
         const int4 m = vmeta[v];
         const int64_t rs = m.x;
         // u is an out-neighbour of v: search the out-part of row v
-        e = lower_index(ncol, rs + m.z, rs + m.y, u);
+        e = exact ? lower_index(ncol, rs + m.z, rs + m.y, u) : rs + m.y;
         c = rs + m.w;
       } else {
         const int64_t rs = nptr[v];
         const int64_t rend = row_len ? rs + row_len[v] : nptr[v + 1];
-        e = lower_index(ncol, rs + dlo[v], rend, u);
+        e = exact ? lower_index(ncol, rs + dlo[v], rend, u) : rend;
         // first entry >= r1, searched in the stored prefix
         c = lower_index(ncol, rs, e, (int32_t)r1);
       }
