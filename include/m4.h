@@ -228,7 +228,7 @@ int m4_edge_triangles(m4_ctx* ctx, const m4_csr* g, const m4_opts* opts,
  * (M4_EINVAL).  M4_EOVERFLOW when a count is >= 2^64, M4_EINTERNAL when the
  * per-vertex inverse is inconsistent.  The graph and 8n words of statistics
  * stay resident, plus the 4-cycle counters (4n bytes per workgroup, 8n from
- * degree 2^16; at most 8 GiB in all). */
+ * degree 2^16; at most one workgroup per CU and 16 GiB in all). */
 int m4_count_orbits4(m4_ctx* ctx, const m4_csr* g, const m4_opts* opts, uint64_t* orbits);
 
 /* --------------------------------------------------------------- tuning --

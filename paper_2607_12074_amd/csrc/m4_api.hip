@@ -564,7 +564,8 @@ extern "C" int m4_count_orbits4(m4_ctx* ctx, const m4_csr* g, const m4_opts* o,
   tri_run(P, ctx->scal, tu, flags, 0, a, s, ctx->num_cu, big, nullptr);
   // statistics (8 n words) and the bitmap slices of out-degrees above the
   // LDS bound in big2; the 4-cycle counters (4 n bytes per workgroup, 8 n
-  // from degree 2^16, at most 8 GiB, at most 4 workgroups per CU) in big
+  // from degree 2^16, at most 16 GiB, at most one workgroup per CU: more
+  // workgroups measured slower, their counters crowding the caches) in big
   const int kmax = local_dplus_max(P, ctx->scal, s);
   const size_t arr_bytes = align256((size_t)n * 8 * 8);
   int gblocks = 0;
@@ -578,7 +579,7 @@ extern "C" int m4_count_orbits4(m4_ctx* ctx, const m4_csr* g, const m4_opts* o,
   const bool wide = C.dmax >= 65536;
   const int64_t cword = wide ? 8 : 4;
   const int cblocks = (int)std::max<int64_t>(
-      1, std::min<int64_t>((int64_t(8) << 30) / ((int64_t)n * cword), 4 * (int64_t)ctx->num_cu));
+      1, std::min<int64_t>((int64_t(16) << 30) / ((int64_t)n * cword), (int64_t)ctx->num_cu));
   ctx->big.ensure((size_t)cblocks * (size_t)n * (size_t)cword, s);
   unsigned long long* dst = reinterpret_cast<unsigned long long*>(orbits);
   if (!g->on_device) {
