@@ -57,6 +57,7 @@ constexpr int LOC_W_LDS = LOC_K_LDS / 64;  // its words per row
 constexpr int LOC_SINGLE = 65536;          // heaviest 4-cycle owners taken one at a time
 constexpr int LOC_CHUNK = 32;              // ... the rest in runs of this many ranks
 constexpr int LOC_TRI_CHUNK = 16;          // triangle owners per grab
+constexpr int CYC_NT = 512, CYC_NW = CYC_NT / WAVE;  // 4-cycle credits: 8 wavefronts per counter array
 constexpr int ERR_LOCAL = 8;               // an orbit inverse went negative
 
 struct LocIn {
@@ -345,7 +346,7 @@ __global__ __launch_bounds__(LOC_NT) void k_loc_cliques(LocIn in, LocArrays L, i
 // clears the counter.  An endpoint's wedges come from distinct lower
 // neighbours of u, so 16-bit halves hold them while degrees stay below 2^16.
 template <typename CT>
-__global__ __launch_bounds__(LOC_NT) void k_loc_cycles(LocIn in, int64_t r1, LocArrays L,
+__global__ __launch_bounds__(CYC_NT) void k_loc_cycles(LocIn in, int64_t r1, LocArrays L,
                                                        CT* cscr, unsigned int* work) {
   constexpr int HALF = (int)sizeof(CT) * 4;
   constexpr CT LOC_LOW = (CT(1) << HALF) - 1;
@@ -375,7 +376,7 @@ __global__ __launch_bounds__(LOC_NT) void k_loc_cycles(LocIn in, int64_t r1, Loc
       // pass 1: c[w] for the wedges u - v - w with v, w below u; the old
       // values sum to the cycles at u
       unsigned long long pairs = 0;
-      for (int i = wv; i < nl; i += LOC_NW) {
+      for (int i = wv; i < nl; i += CYC_NW) {
         const int32_t v = in.ncol[ub + i];
         const int64_t vb = in.nptr[v];
         const int64_t pe = lower_index(in.ncol, vb, vb + in.dr[v], (int32_t)u);
@@ -386,7 +387,7 @@ __global__ __launch_bounds__(LOC_NT) void k_loc_cycles(LocIn in, int64_t r1, Loc
       // pass 2: a middle vertex v shares each of its wedges with c[w] - 1
       // others; the c[w]-th visit of w gives w its C(c[w], 2) cycles with
       // u and clears the counter
-      for (int i = wv; i < nl; i += LOC_NW) {
+      for (int i = wv; i < nl; i += CYC_NW) {
         const int32_t v = in.ncol[ub + i];
         const int64_t vb = in.nptr[v];
         const int64_t pe = lower_index(in.ncol, vb, vb + in.dr[v], (int32_t)u);
@@ -404,7 +405,7 @@ __global__ __launch_bounds__(LOC_NT) void k_loc_cycles(LocIn in, int64_t r1, Loc
         acc = group_sum<WAVE>(acc);
         if (lane == 0 && acc) atomicAdd(&L.N8[v], acc);
       }
-      block_add_u64<LOC_NT>(&L.N8[u], pairs);
+      block_add_u64<CYC_NT>(&L.N8[u], pairs);
     }
   }
 }
@@ -512,10 +513,10 @@ void local_orbits(const Prep& P, const Classes& C, Scal* scal, unsigned long lon
   if (cblocks > 0) {
     fill_u32(cscr, 0, (size_t)cblocks * (size_t)n * (wide ? 2 : 1), s);
     if (wide)
-      k_loc_cycles<unsigned long long><<<(unsigned)cblocks, LOC_NT, 0, s>>>(
+      k_loc_cycles<unsigned long long><<<(unsigned)cblocks, CYC_NT, 0, s>>>(
           in, C.r1, L, reinterpret_cast<unsigned long long*>(cscr), &scal->work[2]);
     else
-      k_loc_cycles<unsigned int><<<(unsigned)cblocks, LOC_NT, 0, s>>>(
+      k_loc_cycles<unsigned int><<<(unsigned)cblocks, CYC_NT, 0, s>>>(
           in, C.r1, L, reinterpret_cast<unsigned int*>(cscr), &scal->work[2]);
   }
   if (b64 > 0) k_loc_final<8><<<grid_for(b64, 8), 256, 0, s>>>(in, 0, b64, L, out, scal);
