@@ -286,7 +286,7 @@ typedef struct {
                             keeps the dense counter windows when its wedge
                             bound is at least this many endpoints per window
                             it needs (0 = never, else 64..2^20, default
-                            8192)                                             */
+                            16384)                                            */
   int32_t probe_w_far;   /* single graph: probe_w when the hub tables exceed
                             the Infinity Cache, so that a probe is a line
                             read from HBM (1..256, default 16)                */

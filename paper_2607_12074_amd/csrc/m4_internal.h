@@ -127,7 +127,7 @@ struct Tuning {
   int c4_bin_win = 6;       // owners above the one-pass medium bound whose endpoints span at
                             // least this many counter windows are binned by window (0: never)
   int c4_bin_cap = 0;       // endpoints of a binning workgroup's scratch (0: 2^20)
-  int c4_bin_dense = 8192;  // endpoints per window from which an owner keeps dense windows (0: never)
+  int c4_bin_dense = 16384; // endpoints per window from which an owner keeps dense windows (0: never)
   int probe_w_far = 16;     // probe_w when the hub tables do not fit in the Infinity Cache
   int tri_wave_far = 64;    // tri_wave_max when the out-lists do not fit in the Infinity Cache
   // weights of the anchor-selection objective, from stage times measured on
