@@ -340,20 +340,33 @@ __global__ __launch_bounds__(LOC_NT) void k_loc_cliques(LocIn in, LocArrays L, i
 }
 
 // 4-cycle owners u (their highest vertex), heaviest first.  Each block keeps
-// n wedge counters of type CT in device scratch, all zero between owners:
-// the low half counts a wedge endpoint's wedges in the first pass, the high
-// half its visits in the second, whose last visitor credits the endpoint and
-// clears the counter.  An endpoint's wedges come from distinct lower
-// neighbours of u, so 16-bit halves hold them while degrees stay below 2^16.
+// n wedge counters of type CT, all zero between owners: the low half counts
+// a wedge endpoint's wedges in the first pass, the high half its visits in
+// the second, whose last visitor credits the endpoint and clears the
+// counter.  An endpoint's wedges come from distinct lower neighbours of u,
+// so 16-bit halves hold them while degrees stay below 2^16.  The counters of
+// the highest ranks (the hubs, where most wedges end) sit in LDS, the rest
+// in the block's slice of device scratch.
+constexpr int LOC_HOT_BYTES = 128 * 1024;
+
+template <typename CT>
+__device__ __forceinline__ CT hot_or_dev_add(CT* hot, CT* c, int32_t w, int64_t hot_base, CT v) {
+  return w >= hot_base ? atomicAdd(&hot[w - hot_base], v) : atomicAdd(&c[w], v);
+}
+
 template <typename CT>
 __global__ __launch_bounds__(CYC_NT) void k_loc_cycles(LocIn in, int64_t r1, LocArrays L,
                                                        CT* cscr, unsigned int* work) {
   constexpr int HALF = (int)sizeof(CT) * 4;
   constexpr CT LOC_LOW = (CT(1) << HALF) - 1;
+  constexpr int HOT = LOC_HOT_BYTES / (int)sizeof(CT);
+  __shared__ CT hot[HOT];
   __shared__ int64_t s_g;
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
   const int64_t n = in.n;
+  const int64_t hot_base = n > HOT ? n - HOT : 0;
   CT* c = cscr + (int64_t)blockIdx.x * n;
+  for (int i = tid; i < HOT; i += CYC_NT) hot[i] = 0;
   for (;;) {
     if (tid == 0) s_g = (int64_t)atomicAdd(work, 1u);
     __syncthreads();
@@ -381,7 +394,8 @@ __global__ __launch_bounds__(CYC_NT) void k_loc_cycles(LocIn in, int64_t r1, Loc
         const int64_t vb = in.nptr[v];
         const int64_t pe = lower_index(in.ncol, vb, vb + in.dr[v], (int32_t)u);
         for (int64_t p = vb + lane; p < pe; p += WAVE)
-          pairs += (unsigned long long)(atomicAdd(&c[in.ncol[p]], CT(1)) & LOC_LOW);
+          pairs += (unsigned long long)(hot_or_dev_add(hot, c, in.ncol[p], hot_base, CT(1)) &
+                                        LOC_LOW);
       }
       __syncthreads();
       // pass 2: a middle vertex v shares each of its wedges with c[w] - 1
@@ -394,11 +408,12 @@ __global__ __launch_bounds__(CYC_NT) void k_loc_cycles(LocIn in, int64_t r1, Loc
         unsigned long long acc = 0;
         for (int64_t p = vb + lane; p < pe; p += WAVE) {
           const int32_t w = in.ncol[p];
-          const CT old = atomicAdd(&c[w], CT(1) << HALF);
+          const CT old = hot_or_dev_add(hot, c, w, hot_base, CT(1) << HALF);
           const unsigned long long k = (unsigned long long)(old & LOC_LOW);
           acc += k - 1;
           if ((unsigned long long)(old >> HALF) == k - 1) {
-            atomicExch(&c[w], CT(0));
+            if (w >= hot_base) atomicExch(&hot[w - hot_base], CT(0));
+            else atomicExch(&c[w], CT(0));
             if (k >= 2) atomicAdd(&L.N8[w], k * (k - 1) / 2);
           }
         }

@@ -55,6 +55,14 @@ def test_random_graphs_match_oracle(ctx, name, make):
     assert orbit_sums_to_counts(got)[0] == ctx.count(*g)
 
 
+def test_counters_in_lds_and_device_memory(ctx):
+    # 50000 vertices: the wedge counters of the top 32768 ranks sit in LDS,
+    # the lower ranks' in device memory; every row still matches the oracle
+    g = gg.gnm(50000, 150000, 9)
+    got = ctx.orbits(*g)
+    assert (got == oracle.orbits_esu(*g)).all()
+
+
 def test_er_workload(ctx):
     gold = json.load(open(os.path.join(HERE, "golden", "er_2000_20000.json")))
     g = gg.gnm(2000, 20000, 1)
