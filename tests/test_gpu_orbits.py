@@ -119,3 +119,27 @@ def test_social_scale18_totals(ctx):
     # at v (paw degree 3, diamond degree 3, clique)
     c = got.astype(object)
     assert (c[:, 3] + c[:, 7] + c[:, 9] + c[:, 10] == d * (d - 1) * (d - 2) // 6).all()
+
+
+def test_validation_stream_and_range_errors(ctx):
+    import torch
+    import paper_2607_12074_amd as m4
+    rp, col = G.gnp(40, 0.2, 1)
+    bad = col.copy()
+    bad[0], bad[1] = bad[1], bad[0]  # unsorted row
+    with pytest.raises(m4.M4Error) as e:
+        ctx.orbits(rp, bad, flags=m4.M4_VALIDATE)
+    assert e.value.code == m4.M4_EINVAL
+    with pytest.raises(m4.M4Error) as e:
+        ctx.orbits(rp, col[:-2])  # row_ptr[n] != nnz
+    assert e.value.code == m4.M4_ERANGE
+    assert (ctx.orbits(rp, col, flags=m4.M4_VALIDATE) == oracle.orbits_brute(rp, col)).all()
+    # on a caller stream, output on the device
+    g = gg.rmat(12, 8, 0.57, 0.19, 0.19, 4)
+    want = ctx.orbits(*g)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        rpd, cold = torch.from_numpy(g[0]).cuda(), torch.from_numpy(g[1]).cuda()
+        got = ctx.orbits(rpd, cold)
+    side.synchronize()
+    assert (got.cpu().numpy().view(np.uint64) == want).all()
